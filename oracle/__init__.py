@@ -1,0 +1,15 @@
+"""FP64 CPU oracle for polynomial-preconditioned FISTA (TEST INFRASTRUCTURE ONLY).
+
+This package is the plain, slow, obviously-correct statement of what the GPU
+library computes, written from the paper (Iyer et al., "Polynomial
+Preconditioners for Regularized Linear Inverse Problems", arXiv 2204.10252).
+It shares no code with the GPU path and must only be imported by the test
+suite, by ``__graft_entry__.smoke()`` and by the CPU-baseline leg of
+``bench.py``.  Nothing in the product library may call it.
+
+Pinned: every function here is checked in ``tests/test_oracle_*.py`` against
+closed forms, theorems of the paper, textbook definitions or brute force.
+"""
+
+from .pfista_oracle import *  # noqa: F401,F403
+from .pfista_oracle import __all__  # noqa: F401

@@ -1,0 +1,267 @@
+"""FP64 oracle: Cartesian SENSE operators, L2-optimal polynomial, Haar prox, PFISTA.
+
+TEST INFRASTRUCTURE: imported only by tests, the smoke check and the CPU
+baseline of the benchmark.  complex128 / float64 / exact rationals throughout.
+
+Conventions (one reading of the paper each; the design notes list them):
+
+* Problem: ``argmin_x 1/2 ||A x - b||^2 + lam ||Psi x||_1`` (the unconstrained
+  problem of the Introduction), with the Cartesian SENSE model ``A = M F S`` of
+  the Cartesian MRI experiment (Section 3.2): S multiplies by each coil map, F
+  is the unitary 2-D DFT with forward exponent ``exp(-2 pi i k n / N)`` and DC at
+  index 0, M keeps the sampled k-space points.
+* Normalisation (Section 3, opening): A is scaled to unit induced norm by a
+  scalar ``L`` (an upper estimate of the largest eigenvalue of ``A^H A``), b to
+  unit l2 norm: ``A' = A / sqrt(L)``, ``b' = b / ||b||``.
+* Psi is the orthonormal 2-D Haar transform with ``levels`` levels in Mallat
+  layout; every coefficient is thresholded, the coarsest approximation included.
+* Arrays carry a leading slice axis: images ``[S, n, n]``, coil maps and k-space
+  ``[S, C, n, n]``, masks ``[S, n, n]`` (2-D) or ``[S, n]`` (one flag per ky
+  row, the same for every kx).  Slices are independent blocks of A.
+"""
+
+from __future__ import annotations
+
+from fractions import Fraction
+
+import numpy as np
+import scipy.fft
+
+__all__ = [
+    "fft2u", "ifft2u", "expand_mask", "forward", "adjoint", "normal",
+    "kspace_data", "l2_poly_coefficients", "poly_eval", "poly_apply",
+    "haar_fwd", "haar_inv", "soft_threshold", "prox_l1_haar", "objective",
+    "data_term", "power_iteration", "pfista", "pfista_step", "normalise",
+]
+
+_SQRT_HALF = np.sqrt(0.5)
+
+
+# ----------------------------------------------------------------------------
+# Forward model (Section 3.2, the Cartesian SENSE model M F S)
+# ----------------------------------------------------------------------------
+
+def fft2u(v: np.ndarray) -> np.ndarray:
+    """Unitary 2-D DFT over the last two axes, natural (DC-at-0) order."""
+    return scipy.fft.fft2(v, axes=(-2, -1), norm="ortho")
+
+
+def ifft2u(v: np.ndarray) -> np.ndarray:
+    """Inverse of ``fft2u`` (its adjoint, since it is unitary)."""
+    return scipy.fft.ifft2(v, axes=(-2, -1), norm="ortho")
+
+
+def expand_mask(mask: np.ndarray, n: int) -> np.ndarray:
+    """Boolean k-space mask ``[S, n, n]`` from a 2-D ``[S, n, n]`` or a
+    phase-encode ``[S, n]`` mask (row ky sampled for every kx)."""
+    m = np.asarray(mask) != 0
+    if m.ndim == 2:
+        m = np.repeat(m[:, :, None], n, axis=2)
+    return m
+
+
+def forward(sens: np.ndarray, mask: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """``A x = M F (S_c x)`` for every coil: ``[S, n, n] -> [S, C, n, n]``."""
+    n = x.shape[-1]
+    m = expand_mask(mask, n)
+    return m[:, None, :, :] * fft2u(sens * x[:, None, :, :])
+
+
+def adjoint(sens: np.ndarray, mask: np.ndarray, y: np.ndarray) -> np.ndarray:
+    """``A^H y = sum_c conj(S_c) F^H (M y_c)``: ``[S, C, n, n] -> [S, n, n]``."""
+    n = y.shape[-1]
+    m = expand_mask(mask, n)
+    return np.sum(np.conj(sens) * ifft2u(m[:, None, :, :] * y), axis=1)
+
+
+def normal(sens: np.ndarray, mask: np.ndarray, x: np.ndarray, scale: float = 1.0) -> np.ndarray:
+    """``scale * A^H A x`` (the normal operator whose spectrum the paper targets)."""
+    return scale * adjoint(sens, mask, forward(sens, mask, x))
+
+
+def kspace_data(sens: np.ndarray, mask: np.ndarray, img: np.ndarray,
+                noise: np.ndarray) -> np.ndarray:
+    """Simulated measurements ``b = M (F S img + noise)`` (noise only where sampled)."""
+    n = img.shape[-1]
+    m = expand_mask(mask, n)
+    return m[:, None, :, :] * (fft2u(sens * img[:, None, :, :]) + noise)
+
+
+def normalise(b: np.ndarray, lam_max: float):
+    """Scalars of the normalisation: returns ``(b / ||b||, ||b||, 1/L)``."""
+    nb = float(np.linalg.norm(b))
+    return b / nb, nb, 1.0 / lam_max
+
+
+def power_iteration(sens: np.ndarray, mask: np.ndarray, v0: np.ndarray, iters: int) -> float:
+    """Largest eigenvalue of ``A^H A`` by power iteration (Section 2, the note
+    that the maximum eigenvalue can be estimated).
+
+    ``v_{i+1} = N v_i / ||N v_i||`` from the given start vector; returns
+    ``||N v_{iters-1}||`` with ``||v_{iters-1}|| = 1`` (all slices form one vector,
+    so the result is the maximum over slices).
+    """
+    v = v0 / np.linalg.norm(v0)
+    est = 0.0
+    for _ in range(iters):
+        w = normal(sens, mask, v)
+        est = float(np.linalg.norm(w))
+        v = w / est
+    return est
+
+
+# ----------------------------------------------------------------------------
+# Polynomial preconditioner (Section 2.5 cost; Section 2.7 evaluation)
+# ----------------------------------------------------------------------------
+
+def l2_poly_coefficients(degree: int) -> list:
+    """Exact coefficients ``c[0..d]`` (ascending powers) of the polynomial that
+    minimises ``int_0^1 (1 - z q(z))^2 dz`` over degree-d polynomials q
+    (Section 2.5, the L2 polynomial cost).
+
+    Setting the derivative in ``c_i`` to zero gives the normal equations
+    ``sum_j c_j / (i + j + 3) = 1 / (i + 2)`` for ``i = 0..d``, solved here by
+    Gaussian elimination over the rationals.
+    """
+    d = int(degree)
+    if d < 0:
+        raise ValueError("degree must be >= 0")
+    a = [[Fraction(1, i + j + 3) for j in range(d + 1)] + [Fraction(1, i + 2)]
+         for i in range(d + 1)]
+    for col in range(d + 1):
+        piv = next(r for r in range(col, d + 1) if a[r][col] != 0)
+        a[col], a[piv] = a[piv], a[col]
+        p = a[col][col]
+        a[col] = [v / p for v in a[col]]
+        for r in range(d + 1):
+            if r != col and a[r][col] != 0:
+                f = a[r][col]
+                a[r] = [vr - f * vc for vr, vc in zip(a[r], a[col])]
+    return [a[i][d + 1] for i in range(d + 1)]
+
+
+def poly_eval(coef, z):
+    """``p(z) = sum_i c[i] z^i`` (the coefficient order of Section 2.7)."""
+    z = np.asarray(z, dtype=np.float64)
+    out = np.zeros_like(z)
+    for c in reversed([float(c) for c in coef]):
+        out = out * z + c
+    return out
+
+
+def poly_apply(sens: np.ndarray, mask: np.ndarray, scale: float, coef, g: np.ndarray) -> np.ndarray:
+    """``p(N') g`` with ``N' = scale * A^H A``, nested as in Listing 1:
+    ``P = c0 I + N'(c1 I + N'(c2 I + ...))``, i.e. ``h = c_d g`` then
+    ``h = c_i g + N' h`` for ``i = d-1, ..., 0`` (d applications of N')."""
+    c = [float(v) for v in coef]
+    h = c[-1] * g
+    for ci in reversed(c[:-1]):
+        h = ci * g + normal(sens, mask, h, scale)
+    return h
+
+
+# ----------------------------------------------------------------------------
+# Regulariser and its proximal operator (Section 2.1 definition)
+# ----------------------------------------------------------------------------
+
+def haar_fwd(x: np.ndarray, levels: int) -> np.ndarray:
+    """Orthonormal separable 2-D Haar analysis over the last two axes, Mallat
+    layout: at each level the current low-pass square is split along x into
+    ``(even + odd)/sqrt2 | (even - odd)/sqrt2`` and then likewise along y."""
+    w = np.array(x, dtype=np.complex128, copy=True)
+    m = w.shape[-1]
+    for _ in range(levels):
+        blk = w[..., :m, :m]
+        lo = (blk[..., :, 0::2] + blk[..., :, 1::2]) * _SQRT_HALF
+        hi = (blk[..., :, 0::2] - blk[..., :, 1::2]) * _SQRT_HALF
+        blk = np.concatenate([lo, hi], axis=-1)
+        lo = (blk[..., 0::2, :] + blk[..., 1::2, :]) * _SQRT_HALF
+        hi = (blk[..., 0::2, :] - blk[..., 1::2, :]) * _SQRT_HALF
+        w[..., :m, :m] = np.concatenate([lo, hi], axis=-2)
+        m //= 2
+    return w
+
+
+def haar_inv(w: np.ndarray, levels: int) -> np.ndarray:
+    """Inverse (= adjoint) of ``haar_fwd``."""
+    x = np.array(w, dtype=np.complex128, copy=True)
+    n = x.shape[-1]
+    for lev in reversed(range(levels)):
+        m = n >> lev
+        h = m // 2
+        blk = x[..., :m, :m].copy()
+        lo, hi = blk[..., :h, :], blk[..., h:, :]
+        cols = np.empty_like(blk)
+        cols[..., 0::2, :] = (lo + hi) * _SQRT_HALF
+        cols[..., 1::2, :] = (lo - hi) * _SQRT_HALF
+        lo, hi = cols[..., :, :h], cols[..., :, h:]
+        rows = np.empty_like(blk)
+        rows[..., :, 0::2] = (lo + hi) * _SQRT_HALF
+        rows[..., :, 1::2] = (lo - hi) * _SQRT_HALF
+        x[..., :m, :m] = rows
+    return x
+
+
+def soft_threshold(w: np.ndarray, lam: float) -> np.ndarray:
+    """Proximal operator of ``lam |.|`` on complex numbers: ``w (1 - lam/|w|)``
+    where ``|w| > lam`` and exactly 0 elsewhere (including w = 0)."""
+    mag = np.abs(w)
+    keep = mag > lam
+    scale = np.zeros_like(mag)
+    np.divide(lam, mag, out=scale, where=keep)
+    return np.where(keep, w * (1.0 - scale), 0.0)
+
+
+def prox_l1_haar(v: np.ndarray, lam: float, levels: int) -> np.ndarray:
+    """``prox_{lam ||Psi .||_1}(v) = Psi^H soft(Psi v, lam)`` (Psi orthonormal)."""
+    return haar_inv(soft_threshold(haar_fwd(v, levels), lam), levels)
+
+
+# ----------------------------------------------------------------------------
+# Objective and the iteration (Algorithms 2 and 4)
+# ----------------------------------------------------------------------------
+
+def data_term(sens, mask, bn, scale, x) -> float:
+    """``1/2 ||sqrt(scale) A x - bn||^2`` computed from the k-space residual."""
+    r = np.sqrt(scale) * forward(sens, mask, x) - bn
+    return 0.5 * float(np.vdot(r, r).real)
+
+
+def objective(sens, mask, bn, scale, x, lam, levels) -> float:
+    """``F(x) = 1/2 ||A' x - b'||^2 + lam ||Psi x||_1`` on normalised A', b'."""
+    return data_term(sens, mask, bn, scale, x) + lam * float(np.sum(np.abs(haar_fwd(x, levels))))
+
+
+def pfista_step(z, pg, x_old, lam, levels, beta):
+    """One prox + momentum update of Algorithm 4:
+    ``x_new = prox(z - P g)``, ``z_new = x_new + beta (x_new - x_old)``."""
+    x_new = prox_l1_haar(z - pg, lam, levels)
+    z_new = x_new + beta * (x_new - x_old)
+    return x_new, z_new
+
+
+def pfista(sens, mask, bn, scale, lam, coef, levels, iters, x0=None, z0=None, k0=0,
+           history=False):
+    """Polynomial-preconditioned FISTA, Algorithm 4 (Algorithm 2 when coef = [1]).
+
+    With ``N' = scale A^H A`` and ``b' = bn`` (already normalised), step k >= 0:
+    ``g = N' z_k - A'^H b'``; ``x_{k+1} = prox(z_k - p(N') g)``;
+    ``beta_k = k / (k + 3)``; ``z_{k+1} = x_{k+1} + beta_k (x_{k+1} - x_k)``,
+    from ``x_0 = z_0 = 0``.  The momentum uses the newest iterate, the usual
+    FISTA form (the printed update names the older pair of iterates).
+
+    Returns ``(x, z, hist)``; ``hist`` holds ``F(x_{k+1})`` per step if asked.
+    Passing ``x0, z0, k0`` resumes from the state after ``k0`` steps.
+    """
+    ahb = scale ** 0.5 * adjoint(sens, mask, bn)
+    x = np.zeros_like(ahb) if x0 is None else np.array(x0, dtype=np.complex128)
+    z = np.zeros_like(ahb) if z0 is None else np.array(z0, dtype=np.complex128)
+    hist = []
+    for k in range(k0, k0 + iters):
+        g = normal(sens, mask, z, scale) - ahb
+        pg = poly_apply(sens, mask, scale, coef, g)
+        beta = k / (k + 3.0)
+        x, z = pfista_step(z, pg, x, lam, levels, beta)
+        if history:
+            hist.append(objective(sens, mask, bn, scale, x, lam, levels))
+    return x, z, hist
