@@ -1,0 +1,199 @@
+/*
+ * pfista: polynomial-preconditioned FISTA for Cartesian SENSE on AMD gfx950.
+ *
+ * Solves  argmin_x 1/2 ||A' x - b'||^2 + lambda ||Psi x||_1   (the unconstrained
+ * problem of the paper's Introduction) with Algorithm 4 of Iyer et al.,
+ * "Polynomial Preconditioners for Regularized Linear Inverse Problems"
+ * (arXiv 2204.10252): FISTA whose gradient A'^H(A' z - b') is multiplied by
+ * p(A'^H A') for a degree-d polynomial p fitted by the L2 cost of Section 2.5
+ * and applied in the nested (Horner) order of Section 2.7.
+ *
+ *   A  = M F S  (Section 3.2, Cartesian SENSE): S multiplies by each coil map,
+ *        F is the unitary 2-D DFT (forward exponent exp(-2 pi i k n / N),
+ *        DC at index 0), M keeps the sampled k-space points;
+ *   A' = sqrt(inv_l) A, b' = b / ||b||  (normalisation of Section 3, with
+ *        inv_l = 1/L and L an upper bound of the top eigenvalue of A^H A);
+ *   Psi = orthonormal 2-D Haar transform with `haar_levels` levels; every
+ *        coefficient (the coarsest approximation too) is soft-thresholded.
+ *
+ * Memory: every array argument is a DEVICE pointer owned by the caller unless
+ * marked "host".  Complex data is complex64 (pfista_c32), row-major with x
+ * fastest:
+ *   image (x, y, w, z, g, ...)   [S][N][N]
+ *   coil maps `sens`             [S][C][N][N]
+ *   k-space `kspace`, `b`        [S][C][N][N]  natural order, zero off-mask
+ *   mask, 2-D kind               uint8 [S][N][N], nonzero = sampled
+ *   mask, phase-encode kind      uint8 [S][N], one flag per ky row (all kx)
+ * with N = desc.n, C = desc.coils, S = desc.slices.  Complex pointers must be
+ * 8-byte aligned; pfista_step needs 16-byte alignment.  `ws` is a caller-owned
+ * device workspace of at least pfista_workspace_bytes() bytes; the library
+ * allocates no device memory and keeps no state between calls.
+ *
+ * Streams: every call enqueues on `stream` and returns without waiting, except
+ * pfista_solve, pfista_data_term and pfista_power_iteration, which wait for
+ * their host-visible scalars (documented per call).  Calls sharing a
+ * workspace must not overlap.
+ *
+ * Errors: functions return PFISTA_OK (0) or a negative pfista_status; the
+ * library never aborts.  pfista_last_error() gives a per-thread message.
+ */
+#ifndef PFISTA_H
+#define PFISTA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  float re, im;
+} pfista_c32;
+
+typedef enum {
+  PFISTA_OK = 0,
+  PFISTA_EINVAL = -1,      /* null, misaligned or aliased pointer; bad size */
+  PFISTA_UNSUPPORTED = -2, /* image side, levels or degree outside the supported set */
+  PFISTA_EHIP = -3,        /* HIP runtime error (message kept) */
+  PFISTA_DIVERGED = -4     /* non-finite or exploding objective in pfista_solve */
+} pfista_status;
+
+typedef enum { PFISTA_MASK_2D = 0, PFISTA_MASK_1D = 1 } pfista_mask_kind;
+
+/* Problem shape.  n in {64, 128, 160, 192, 256, 320, 384, 512} (radices 2, 3,
+ * 5); 1 <= haar_levels <= 4; coils >= 1; slices >= 0; slices * coils <= 65535. */
+typedef struct {
+  int n;
+  int coils;
+  int slices;
+  int haar_levels;
+  int mask_kind; /* pfista_mask_kind */
+} pfista_desc;
+
+typedef struct pfista_plan pfista_plan;
+
+/* Validate `d` and build an immutable plan (host object, plus one-time upload
+ * of FP64-computed twiddle tables to the current device).  Plans may be shared
+ * across streams and threads.  Returns EINVAL / UNSUPPORTED on a bad desc. */
+int pfista_plan_create(pfista_plan **out, const pfista_desc *d);
+void pfista_plan_destroy(pfista_plan *p);
+
+/* Workspace size in bytes needed by every call on this plan (including
+ * pfista_solve at any degree <= 8): one complex64 per (slice, coil, pixel),
+ * five images, and small FP64 scratch. */
+size_t pfista_workspace_bytes(const pfista_plan *p);
+
+/* Normal operator (the paper's A^H A, Section 2.7 counts these):
+ *   y = alpha * A^H A x + beta * w      (A un-normalised; pass alpha = inv_l
+ *                                        for the normalised operator)
+ * w may be NULL (beta ignored) or equal to y; y must not overlap x.
+ * Arithmetic: FP32 complex, FP32 accumulation over coils in a fixed order
+ * (bitwise deterministic). */
+int pfista_normal_apply(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *mask,
+                        const pfista_c32 *x, pfista_c32 *y, float alpha, const pfista_c32 *w,
+                        float beta, void *ws, hipStream_t stream);
+
+/* Polynomial preconditioner (Section 2.7, nested evaluation):
+ *   out = p(N') g,  N' = inv_l * A^H A,  p(z) = sum_{i=0..degree} coef[i] z^i,
+ * evaluated as h = coef[d] g; h = coef[i] g + N' h for i = d-1 .. 0, i.e.
+ * `degree` normal applies.  coef: HOST array of degree+1 doubles (rounded to
+ * FP32 for the kernels).  out must not overlap g.  0 <= degree <= 8. */
+int pfista_poly_apply(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *mask,
+                      double inv_l, const double *coef, int degree, const pfista_c32 *g,
+                      pfista_c32 *out, void *ws, hipStream_t stream);
+
+/* Fused proximal and momentum step of Algorithm 4 (prox of Section 2.1):
+ *   x_new = Psi^H soft(Psi (z - pg), lambda)
+ *   z_new = x_new + beta_k (x_new - x_old)
+ * and red[0] = sum |soft(Psi(z - pg))| (= ||Psi x_new||_1), red[1] =
+ * ||x_new - x_old||^2, red[2] = ||x_new||^2, accumulated in FP64 (red: device,
+ * 3 doubles).  Outputs may alias inputs element for element (in-place update of
+ * x and z is allowed).  Complex soft-threshold: w (1 - lambda/|w|) where
+ * |w| > lambda, else 0.  16-byte aligned pointers required. */
+int pfista_step(const pfista_plan *p, const pfista_c32 *z, const pfista_c32 *pg,
+                const pfista_c32 *x_old, pfista_c32 *x_new, pfista_c32 *z_new, float lambda,
+                float beta_k, double *red, void *ws, hipStream_t stream);
+
+/* Forward model: kspace = M F (S x), zero off-mask. */
+int pfista_forward(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *mask,
+                   const pfista_c32 *x, pfista_c32 *kspace, void *ws, hipStream_t stream);
+
+/* Adjoint: y = alpha * A^H kspace = alpha * sum_c conj(S_c) F^H (M kspace_c). */
+int pfista_adjoint(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *mask,
+                   const pfista_c32 *kspace, pfista_c32 *y, float alpha, void *ws,
+                   hipStream_t stream);
+
+/* Data term 1/2 || sqrt(inv_l) A x - b_scale * b ||^2 from the k-space
+ * residual, reduced in FP64.  Waits for the stream; *out is HOST. */
+int pfista_data_term(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *mask,
+                     const pfista_c32 *b, const pfista_c32 *x, double inv_l, double b_scale,
+                     double *out, void *ws, hipStream_t stream);
+
+/* Power iteration for the top eigenvalue of A^H A (the normalisation scalar
+ * of Section 3): v <- N v / ||N v|| for `iters` steps; *lam_max (HOST) =
+ * ||N v|| of the last step.  v: device image, the start vector on entry (if
+ * NULL, an internal SplitMix64-seeded vector in the workspace is used) and the
+ * last iterate on exit.  Waits for the stream. */
+int pfista_power_iteration(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *mask,
+                           pfista_c32 *v, int iters, double *lam_max, void *ws,
+                           hipStream_t stream);
+
+/* L2-optimal coefficients of Section 2.5 (minimise int_0^1 (1 - z q(z))^2 dz),
+ * ascending powers, into HOST coef[0..degree]; exact integer sums through the
+ * shifted-Legendre kernel, one final rounding.  0 <= degree <= 8. */
+int pfista_poly_coefficients(int degree, double *coef);
+
+typedef struct {
+  double lambda;       /* l1 weight in normalised units */
+  double inv_l;        /* 1/L > 0; 0: estimate L = 1.01 * power iteration */
+  int power_iters;     /* power-iteration steps when inv_l == 0 (e.g. 30) */
+  int degree;          /* polynomial degree d >= 0 (d + 1 normal applies/iter) */
+  const double *coef;  /* HOST, degree+1 coefficients; NULL: L2-optimal fit.
+                          Plain FISTA (Algorithm 2) is degree 0, coef = {1}. */
+  int max_iter;        /* iterations to run (>= 0) */
+  int check_every;     /* host check / history interval, 1..4096 */
+  double tol;          /* stop when ||x_k+1 - x_k|| <= tol ||x_k+1|| at a check; 0 off */
+  double f_stop;       /* stop when F(x_k) <= f_stop at a check; 0 off */
+  int eval_objective;  /* evaluate F(x_k) at each check (one residual pass) */
+  int k0;              /* resume: iterations already done; x_io, z_io hold x_k0, z_k0 */
+  int graph_iters;     /* > 0: replay the loop as a HIP graph of this many
+                          iterations (needs a non-default stream); 0: launches */
+} pfista_params;
+
+typedef struct {
+  int iters;              /* iterations run in this call */
+  int status;             /* pfista_status of the run */
+  double objective;       /* last evaluated F (NaN if none) */
+  double rel_change;      /* ||x_k - x_k-1|| / ||x_k|| at the last check */
+  double l1;              /* ||Psi x_k||_1 at the last check */
+  double inv_l;           /* 1/L used */
+  double bnorm;           /* ||b|| */
+  long long normal_applies; /* A^H A applications in the loop */
+} pfista_report;
+
+/* Algorithm 4 on the caller's stream.  Setup (FP64 ||b||, optional power
+ * iteration, exact coefficients, A'^H b') then max_iter iterations
+ *   g = N' z - A'^H b';  pg = p(N') g;  x, z <- pfista_step(z, pg, x, beta_k),
+ * beta_k = k / (k + 3), x_0 = z_0 = 0 unless resuming (k0 > 0).  The stream is
+ * synchronised only at checks (every check_every iterations) and on return.
+ * x_io: device image, output x_k (input x_k0 when resuming).  z_io: device
+ * image for the momentum point (may be NULL when k0 == 0).  history (HOST,
+ * nullable): F(x) after each check, ceil(max_iter / check_every) doubles, when
+ * eval_objective.  Returns DIVERGED (and stops) on a non-finite value or an
+ * objective above 10 F(0) = 5. */
+int pfista_solve(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *mask,
+                 const pfista_c32 *b, const pfista_params *prm, pfista_c32 *x_io,
+                 pfista_c32 *z_io, double *history, pfista_report *rep, void *ws,
+                 hipStream_t stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *pfista_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PFISTA_H */

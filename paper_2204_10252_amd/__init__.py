@@ -1,0 +1,291 @@
+"""Python binding of libpfista (polynomial-preconditioned FISTA on gfx950).
+
+Argument marshalling only: every function forwards device pointers of
+``torch`` tensors (complex64 images / coil data, uint8 masks) and the current
+HIP stream to the C-ABI of ``include/pfista.h``; all arithmetic runs in the
+library's kernels.  Importing needs the built ``libpfista.so`` next to this
+file (``python -m paper_2204_10252_amd.build``); there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+__all__ = [
+    "Plan", "PfistaError", "load_library", "library_path", "poly_coefficients",
+    "normal_apply", "poly_apply", "step", "forward", "adjoint", "data_term",
+    "power_iteration", "solve", "MASK_2D", "MASK_1D", "header_functions",
+]
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+MASK_2D, MASK_1D = 0, 1
+OK, EINVAL, UNSUPPORTED, EHIP, DIVERGED = 0, -1, -2, -3, -4
+
+
+class PfistaError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"pfista error {code}: {msg}")
+        self.code = code
+
+
+class _Desc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("coils", ctypes.c_int), ("slices", ctypes.c_int),
+                ("haar_levels", ctypes.c_int), ("mask_kind", ctypes.c_int)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("lambda_", ctypes.c_double), ("inv_l", ctypes.c_double),
+                ("power_iters", ctypes.c_int), ("degree", ctypes.c_int),
+                ("coef", ctypes.POINTER(ctypes.c_double)), ("max_iter", ctypes.c_int),
+                ("check_every", ctypes.c_int), ("tol", ctypes.c_double),
+                ("f_stop", ctypes.c_double), ("eval_objective", ctypes.c_int),
+                ("k0", ctypes.c_int), ("graph_iters", ctypes.c_int)]
+
+
+class _Report(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("status", ctypes.c_int), ("objective", ctypes.c_double),
+                ("rel_change", ctypes.c_double), ("l1", ctypes.c_double), ("inv_l", ctypes.c_double),
+                ("bnorm", ctypes.c_double), ("normal_applies", ctypes.c_longlong)]
+
+
+_VP, _I, _F, _D = ctypes.c_void_p, ctypes.c_int, ctypes.c_float, ctypes.c_double
+_SIGS = {
+    "pfista_plan_create": (_I, [ctypes.POINTER(_VP), ctypes.POINTER(_Desc)]),
+    "pfista_plan_destroy": (None, [_VP]),
+    "pfista_workspace_bytes": (ctypes.c_size_t, [_VP]),
+    "pfista_normal_apply": (_I, [_VP, _VP, _VP, _VP, _VP, _F, _VP, _F, _VP, _VP]),
+    "pfista_poly_apply": (_I, [_VP, _VP, _VP, _D, ctypes.POINTER(_D), _I, _VP, _VP, _VP, _VP]),
+    "pfista_step": (_I, [_VP, _VP, _VP, _VP, _VP, _VP, _F, _F, _VP, _VP, _VP]),
+    "pfista_forward": (_I, [_VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "pfista_adjoint": (_I, [_VP, _VP, _VP, _VP, _VP, _F, _VP, _VP]),
+    "pfista_data_term": (_I, [_VP, _VP, _VP, _VP, _VP, _D, _D, ctypes.POINTER(_D), _VP, _VP]),
+    "pfista_power_iteration": (_I, [_VP, _VP, _VP, _VP, _I, ctypes.POINTER(_D), _VP, _VP]),
+    "pfista_poly_coefficients": (_I, [_I, ctypes.POINTER(_D)]),
+    "pfista_solve": (_I, [_VP, _VP, _VP, _VP, ctypes.POINTER(_Params), _VP, _VP,
+                          ctypes.POINTER(_D), ctypes.POINTER(_Report), _VP, _VP]),
+    "pfista_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def library_path() -> str:
+    return os.path.join(HERE, "libpfista.so")
+
+
+def load_library():
+    """Load libpfista.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        path = library_path()
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is missing: build it with `python -m paper_2204_10252_amd.build`")
+        lib = ctypes.CDLL(path)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype, fn.argtypes = res, args
+        _lib = lib
+    return _lib
+
+
+def header_functions() -> list:
+    """Names of the functions declared in include/pfista.h."""
+    with open(os.path.join(ROOT, "include", "pfista.h")) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pfista_\w+)\s*\(", text)))
+
+
+def _check(rc):
+    if rc != OK:
+        msg = load_library().pfista_last_error().decode()
+        raise PfistaError(rc, msg)
+    return rc
+
+
+# ------------------------------------------------------------------ marshalling
+
+def _ptr(t, name, dtype=None, numel=None, allow_none=False):
+    if t is None:
+        if allow_none:
+            return None
+        raise ValueError(f"{name} is required")
+    import torch
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """Owns a ``pfista_plan`` and a device workspace sized for it."""
+
+    def __init__(self, n, coils, slices, haar_levels=4, mask_kind=MASK_2D, device=None):
+        import torch
+        lib = load_library()
+        self.n, self.coils, self.slices = int(n), int(coils), int(slices)
+        self.haar_levels, self.mask_kind = int(haar_levels), int(mask_kind)
+        desc = _Desc(self.n, self.coils, self.slices, self.haar_levels, self.mask_kind)
+        h = ctypes.c_void_p()
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        with torch.cuda.device(self.device):
+            _check(lib.pfista_plan_create(ctypes.byref(h), ctypes.byref(desc)))
+        self._h = h
+        nbytes = int(lib.pfista_workspace_bytes(h))
+        self.ws = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=self.device)
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def n_img(self):
+        return self.slices * self.n * self.n
+
+    @property
+    def n_coil(self):
+        return self.slices * self.coils * self.n * self.n
+
+    @property
+    def mask_numel(self):
+        return self.slices * self.n * (self.n if self.mask_kind == MASK_2D else 1)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.pfista_plan_destroy(h)
+            self._h = None
+
+
+def _cplx():
+    import torch
+    return torch.complex64
+
+
+def _u8():
+    import torch
+    return torch.uint8
+
+
+def poly_coefficients(degree: int) -> list:
+    lib = load_library()
+    buf = (ctypes.c_double * (degree + 1))()
+    _check(lib.pfista_poly_coefficients(int(degree), buf))
+    return list(buf)
+
+
+def normal_apply(plan, sens, mask, x, y, alpha=1.0, w=None, beta=0.0, stream=None):
+    c = _cplx()
+    _check(load_library().pfista_normal_apply(
+        plan.handle, _ptr(sens, "sens", c, plan.n_coil), _ptr(mask, "mask", _u8(), plan.mask_numel),
+        _ptr(x, "x", c, plan.n_img), _ptr(y, "y", c, plan.n_img), float(alpha),
+        _ptr(w, "w", c, plan.n_img, allow_none=True), float(beta), _ptr(plan.ws, "ws"), _stream(stream)))
+    return y
+
+
+def poly_apply(plan, sens, mask, inv_l, coef, g, out, stream=None):
+    c = _cplx()
+    arr = (ctypes.c_double * len(coef))(*[float(v) for v in coef])
+    _check(load_library().pfista_poly_apply(
+        plan.handle, _ptr(sens, "sens", c, plan.n_coil), _ptr(mask, "mask", _u8(), plan.mask_numel),
+        float(inv_l), arr, len(coef) - 1, _ptr(g, "g", c, plan.n_img), _ptr(out, "out", c, plan.n_img),
+        _ptr(plan.ws, "ws"), _stream(stream)))
+    return out
+
+
+def step(plan, z, pg, x_old, x_new, z_new, lam, beta_k, red, stream=None):
+    import torch
+    c = _cplx()
+    _check(load_library().pfista_step(
+        plan.handle, _ptr(z, "z", c, plan.n_img), _ptr(pg, "pg", c, plan.n_img),
+        _ptr(x_old, "x_old", c, plan.n_img), _ptr(x_new, "x_new", c, plan.n_img),
+        _ptr(z_new, "z_new", c, plan.n_img), float(lam), float(beta_k),
+        _ptr(red, "red", torch.float64, 3), _ptr(plan.ws, "ws"), _stream(stream)))
+
+
+def forward(plan, sens, mask, x, kspace, stream=None):
+    c = _cplx()
+    _check(load_library().pfista_forward(
+        plan.handle, _ptr(sens, "sens", c, plan.n_coil), _ptr(mask, "mask", _u8(), plan.mask_numel),
+        _ptr(x, "x", c, plan.n_img), _ptr(kspace, "kspace", c, plan.n_coil), _ptr(plan.ws, "ws"),
+        _stream(stream)))
+    return kspace
+
+
+def adjoint(plan, sens, mask, kspace, y, alpha=1.0, stream=None):
+    c = _cplx()
+    _check(load_library().pfista_adjoint(
+        plan.handle, _ptr(sens, "sens", c, plan.n_coil), _ptr(mask, "mask", _u8(), plan.mask_numel),
+        _ptr(kspace, "kspace", c, plan.n_coil), _ptr(y, "y", c, plan.n_img), float(alpha),
+        _ptr(plan.ws, "ws"), _stream(stream)))
+    return y
+
+
+def data_term(plan, sens, mask, b, x, inv_l, b_scale, stream=None) -> float:
+    c = _cplx()
+    out = ctypes.c_double()
+    _check(load_library().pfista_data_term(
+        plan.handle, _ptr(sens, "sens", c, plan.n_coil), _ptr(mask, "mask", _u8(), plan.mask_numel),
+        _ptr(b, "b", c, plan.n_coil), _ptr(x, "x", c, plan.n_img), float(inv_l), float(b_scale),
+        ctypes.byref(out), _ptr(plan.ws, "ws"), _stream(stream)))
+    return out.value
+
+
+def power_iteration(plan, sens, mask, iters, v=None, stream=None) -> float:
+    c = _cplx()
+    out = ctypes.c_double()
+    _check(load_library().pfista_power_iteration(
+        plan.handle, _ptr(sens, "sens", c, plan.n_coil), _ptr(mask, "mask", _u8(), plan.mask_numel),
+        _ptr(v, "v", c, plan.n_img, allow_none=True), int(iters), ctypes.byref(out),
+        _ptr(plan.ws, "ws"), _stream(stream)))
+    return out.value
+
+
+def solve(plan, sens, mask, b, x, lam, degree=3, coef=None, max_iter=50, inv_l=0.0, power_iters=30,
+          check_every=None, tol=0.0, f_stop=0.0, eval_objective=False, z=None, k0=0, graph_iters=0,
+          history=False, stream=None, raise_on_diverge=True):
+    """Algorithm 4 through ``pfista_solve``; returns the report as a dict (with
+    ``history`` when asked)."""
+    c = _cplx()
+    lib = load_library()
+    ce = max_iter if check_every is None else check_every
+    ce = max(1, min(int(ce), 4096))
+    carr = None
+    if coef is not None:
+        carr = (ctypes.c_double * len(coef))(*[float(v) for v in coef])
+        degree = len(coef) - 1
+    prm = _Params(float(lam), float(inv_l), int(power_iters), int(degree),
+                  ctypes.cast(carr, ctypes.POINTER(ctypes.c_double)) if carr is not None else None,
+                  int(max_iter), ce, float(tol), float(f_stop), int(bool(eval_objective or history)),
+                  int(k0), int(graph_iters))
+    nh = max(1, -(-int(max_iter) // ce))
+    hist = (ctypes.c_double * nh)() if history else None
+    rep = _Report()
+    rc = lib.pfista_solve(plan.handle, _ptr(sens, "sens", c, plan.n_coil),
+                          _ptr(mask, "mask", _u8(), plan.mask_numel), _ptr(b, "b", c, plan.n_coil),
+                          ctypes.byref(prm), _ptr(x, "x", c, plan.n_img),
+                          _ptr(z, "z", c, plan.n_img, allow_none=True),
+                          ctypes.cast(hist, ctypes.POINTER(ctypes.c_double)) if hist is not None else None,
+                          ctypes.byref(rep), _ptr(plan.ws, "ws"), _stream(stream))
+    out = {k: getattr(rep, k) for k, _ in _Report._fields_}
+    if history:
+        nchk = -(-int(rep.iters) // ce) if rep.iters else 0
+        out["history"] = list(hist)[:nchk]
+    if rc != OK and not (rc == DIVERGED and not raise_on_diverge):
+        _check(rc)
+    out["rc"] = rc
+    return out

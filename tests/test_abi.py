@@ -1,0 +1,62 @@
+"""The C-ABI library on the CPU: it loads, exports every function the header
+declares, and its host-only parts behave (no GPU is touched here)."""
+
+import ctypes
+import os
+
+import pytest
+
+import oracle as orc
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2204_10252_amd as pf
+    if not os.path.exists(pf.library_path()):
+        from paper_2204_10252_amd import build
+        build.build(verbose=False)
+    return pf.load_library()
+
+
+def test_exports_every_declared_function(lib):
+    import paper_2204_10252_amd as pf
+    names = pf.header_functions()
+    assert len(names) >= 13
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(pf._SIGS)
+
+
+def test_host_coefficients_match_oracle(lib):
+    import paper_2204_10252_amd as pf
+    for d in range(9):
+        want = [float(c) for c in orc.l2_poly_coefficients(d)]
+        got = pf.poly_coefficients(d)
+        assert got == pytest.approx(want, rel=4e-16, abs=0)
+    with pytest.raises(pf.PfistaError) as e:
+        pf.poly_coefficients(9)
+    assert e.value.code == pf.UNSUPPORTED
+
+
+def _desc(n=64, coils=2, slices=1, levels=3, kind=0):
+    import paper_2204_10252_amd as pf
+    return pf._Desc(n, coils, slices, levels, kind)
+
+
+@pytest.mark.parametrize("desc,code", [
+    (dict(n=100), -2), (dict(n=96), -2), (dict(levels=0), -2), (dict(levels=5), -2),
+    (dict(coils=0), -1), (dict(slices=-1), -1), (dict(kind=7), -1),
+    (dict(coils=1000, slices=100), -2),
+])
+def test_plan_validation_before_any_gpu_call(lib, desc, code):
+    h = ctypes.c_void_p()
+    d = _desc(**desc)
+    rc = lib.pfista_plan_create(ctypes.byref(h), ctypes.byref(d))
+    assert rc == code
+    assert lib.pfista_last_error().decode()
+
+
+def test_null_plan_is_rejected(lib):
+    rc = lib.pfista_normal_apply(None, None, None, None, None, 1.0, None, 0.0, None, None)
+    assert rc == -1
+    assert b"plan" in lib.pfista_last_error()

@@ -1,0 +1,137 @@
+"""GPU parity of the full PFISTA solve (Algorithm 4) against the FP64 oracle.
+
+Both sides get the same complex64 inputs, the same k-space data (formed by
+the oracle in FP64, then rounded) and the same normalisation scalar (the
+oracle's FP64 power iteration, 100 steps from the seeded start vector, with a
+1 % margin).  Bar: relative l2 error of the final iterate <= 1e-4.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as orc
+from synth import make_inputs, power_start_vector
+from tests.gpu_util import c64, rel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def problem(wid, slices=None):
+    inp = make_inputs(wid, slices)
+    sens = c64(inp["sens"])
+    s128 = sens.astype(np.complex128)
+    img = inp["phantom"]
+    b = c64(orc.kspace_data(s128, inp["mask"], img, inp["noise"]))
+    lam_max = orc.power_iteration(s128, inp["mask"], power_start_vector(inp["n"], inp["slices"]), 100)
+    inv_l = 1.0 / (1.01 * lam_max)
+    bn = b.astype(np.complex128) / np.linalg.norm(b.astype(np.complex128))
+    return inp, sens, s128, b, bn, inv_l
+
+
+def gpu_plan(inp):
+    import paper_2204_10252_amd as pf
+    return pf.Plan(inp["n"], inp["coils"], inp["slices"], haar_levels=inp["levels"],
+                   mask_kind=pf.MASK_1D if inp["mask_kind"] == "1d" else pf.MASK_2D)
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return problem(1)
+
+
+@pytest.mark.parametrize("degree", [None, 1, 3, 5])
+def test_solve_workload1(c1, degree):
+    import torch
+    import paper_2204_10252_amd as pf
+    inp, sens, s128, b, bn, inv_l = c1
+    plan = gpu_plan(inp)
+    coef = [1.0] if degree is None else [float(c) for c in orc.l2_poly_coefficients(degree)]
+    x = torch.empty((1, inp["n"], inp["n"]), dtype=torch.complex64, device="cuda")
+    rep = pf.solve(plan, to_dev(sens), to_dev(inp["mask"]), to_dev(b), x, inp["lam"], coef=coef,
+                   max_iter=50, inv_l=inv_l, eval_objective=True)
+    xo, _, hist = orc.pfista(s128, inp["mask"], bn, inv_l, inp["lam"], coef, inp["levels"], 50,
+                             history=True)
+    assert rel(x.cpu().numpy(), xo) <= 1e-4
+    assert rep["objective"] == pytest.approx(hist[-1], rel=1e-5)
+    assert rep["iters"] == 50 and rep["normal_applies"] == 50 * len(coef)
+
+
+def test_solve_workload2_short():
+    import torch
+    import paper_2204_10252_amd as pf
+    inp, sens, s128, b, bn, inv_l = problem(2)
+    plan = gpu_plan(inp)
+    coef = [float(c) for c in orc.l2_poly_coefficients(3)]
+    x = torch.empty((1, 256, 256), dtype=torch.complex64, device="cuda")
+    pf.solve(plan, to_dev(sens), to_dev(inp["mask"]), to_dev(b), x, inp["lam"], coef=coef,
+             max_iter=15, inv_l=inv_l)
+    xo, _, _ = orc.pfista(s128, inp["mask"], bn, inv_l, inp["lam"], coef, inp["levels"], 15)
+    assert rel(x.cpu().numpy(), xo) <= 1e-4
+
+
+def test_history_resume_and_graph_are_consistent(c1):
+    import torch
+    import paper_2204_10252_amd as pf
+    inp, sens, s128, b, bn, inv_l = c1
+    plan = gpu_plan(inp)
+    ts, tm, tb = to_dev(sens), to_dev(inp["mask"]), to_dev(b)
+    shp = (1, inp["n"], inp["n"])
+    # per-iteration objective history against the oracle's
+    x = torch.empty(shp, dtype=torch.complex64, device="cuda")
+    rep = pf.solve(plan, ts, tm, tb, x, inp["lam"], degree=2, max_iter=12, inv_l=inv_l,
+                   check_every=1, history=True)
+    _, _, hist = orc.pfista(s128, inp["mask"], bn, inv_l, inp["lam"],
+                            orc.l2_poly_coefficients(2), inp["levels"], 12, history=True)
+    np.testing.assert_allclose(rep["history"], hist, rtol=1e-5)
+    # 20 iterations == 10 + resumed 10, bit for bit
+    xa, za = torch.empty(shp, dtype=torch.complex64, device="cuda"), torch.empty(shp, dtype=torch.complex64, device="cuda")
+    pf.solve(plan, ts, tm, tb, xa, inp["lam"], degree=2, max_iter=20, inv_l=inv_l, z=za)
+    xb, zb = torch.empty_like(xa), torch.empty_like(za)
+    pf.solve(plan, ts, tm, tb, xb, inp["lam"], degree=2, max_iter=10, inv_l=inv_l, z=zb)
+    pf.solve(plan, ts, tm, tb, xb, inp["lam"], degree=2, max_iter=10, inv_l=inv_l, z=zb, k0=10)
+    assert torch.equal(xa, xb) and torch.equal(za, zb)
+    # a captured HIP graph replays exactly the launched iterations
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        xg = torch.empty_like(xa)
+        pf.solve(plan, ts, tm, tb, xg, inp["lam"], degree=2, max_iter=20, inv_l=inv_l,
+                 check_every=10, graph_iters=5, stream=s)
+    s.synchronize()
+    assert torch.equal(xa, xg)
+
+
+def test_power_iteration_estimate_in_solve(c1):
+    import torch
+    import paper_2204_10252_amd as pf
+    inp, sens, s128, b, bn, inv_l = c1
+    plan = gpu_plan(inp)
+    x = torch.empty((1, inp["n"], inp["n"]), dtype=torch.complex64, device="cuda")
+    rep = pf.solve(plan, to_dev(sens), to_dev(inp["mask"]), to_dev(b), x, inp["lam"], degree=3,
+                   max_iter=1, inv_l=0.0, power_iters=100)
+    assert rep["inv_l"] == pytest.approx(inv_l, rel=1e-3)
+    assert rep["bnorm"] == pytest.approx(np.linalg.norm(b.astype(np.complex128)), rel=1e-6)
+
+
+def test_literal_degree_zero_fit_is_reported_as_divergence(c1):
+    import torch
+    import paper_2204_10252_amd as pf
+    inp, sens, s128, b, bn, inv_l = c1
+    plan = gpu_plan(inp)
+    x = torch.empty((1, inp["n"], inp["n"]), dtype=torch.complex64, device="cuda")
+    rep = pf.solve(plan, to_dev(sens), to_dev(inp["mask"]), to_dev(b), x, inp["lam"], coef=[1.5],
+                   max_iter=400, inv_l=inv_l * 1.01, check_every=20, eval_objective=True,
+                   raise_on_diverge=False)
+    assert rep["rc"] == pf.DIVERGED and rep["iters"] < 400
+
+
+def test_lambda_zero_matches_oracle(c1):
+    import torch
+    import paper_2204_10252_amd as pf
+    inp, sens, s128, b, bn, inv_l = c1
+    plan = gpu_plan(inp)
+    x = torch.empty((1, inp["n"], inp["n"]), dtype=torch.complex64, device="cuda")
+    pf.solve(plan, to_dev(sens), to_dev(inp["mask"]), to_dev(b), x, 0.0, degree=2, max_iter=40,
+             inv_l=inv_l)
+    xo, _, _ = orc.pfista(s128, inp["mask"], bn, inv_l, 0.0, orc.l2_poly_coefficients(2),
+                          inp["levels"], 40)
+    assert rel(x.cpu().numpy(), xo) <= 1e-4
