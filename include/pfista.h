@@ -146,6 +146,16 @@ int pfista_power_iteration(const pfista_plan *p, const pfista_c32 *sens, const u
  * shifted-Legendre kernel, one final rounding.  0 <= degree <= 8. */
 int pfista_poly_coefficients(int degree, double *coef);
 
+/* Per-pass timing of the normal operator (y = A^H A x): runs `reps` applies,
+ * recording HIP events on `stream` between the kernel passes, and returns the
+ * average duration of each pass in HOST pass_ms (ms) with their count in
+ * *npasses (3 for a 2-D mask: row transforms, column transform pair, row
+ * inverse + coil combine; 1 for a phase-encode mask).  pass_ms must hold 3
+ * floats.  Synchronous.  For profiling only; results equal pfista_normal_apply. */
+int pfista_profile_normal(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *mask,
+                          const pfista_c32 *x, pfista_c32 *y, int reps, float *pass_ms, int *npasses,
+                          void *ws, hipStream_t stream);
+
 typedef struct {
   double lambda;       /* l1 weight in normalised units */
   double inv_l;        /* 1/L > 0; 0: estimate L = 1.01 * power iteration */

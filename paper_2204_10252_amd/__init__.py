@@ -16,7 +16,7 @@ import re
 __all__ = [
     "Plan", "PfistaError", "load_library", "library_path", "poly_coefficients",
     "normal_apply", "poly_apply", "step", "forward", "adjoint", "data_term",
-    "power_iteration", "solve", "MASK_2D", "MASK_1D", "header_functions",
+    "power_iteration", "profile_normal", "solve", "MASK_2D", "MASK_1D", "header_functions",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -66,6 +66,8 @@ _SIGS = {
     "pfista_poly_coefficients": (_I, [_I, ctypes.POINTER(_D)]),
     "pfista_solve": (_I, [_VP, _VP, _VP, _VP, ctypes.POINTER(_Params), _VP, _VP,
                           ctypes.POINTER(_D), ctypes.POINTER(_Report), _VP, _VP]),
+    "pfista_profile_normal": (_I, [_VP, _VP, _VP, _VP, _VP, _I, ctypes.POINTER(_F),
+                                   ctypes.POINTER(_I), _VP, _VP]),
     "pfista_last_error": (ctypes.c_char_p, []),
 }
 
@@ -73,7 +75,8 @@ _lib = None
 
 
 def library_path() -> str:
-    return os.path.join(HERE, "libpfista.so")
+    """The in-tree build; PFISTA_LIBRARY may name another build of the same sources."""
+    return os.environ.get("PFISTA_LIBRARY") or os.path.join(HERE, "libpfista.so")
 
 
 def load_library():
@@ -253,6 +256,18 @@ def power_iteration(plan, sens, mask, iters, v=None, stream=None) -> float:
         _ptr(v, "v", c, plan.n_img, allow_none=True), int(iters), ctypes.byref(out),
         _ptr(plan.ws, "ws"), _stream(stream)))
     return out.value
+
+
+def profile_normal(plan, sens, mask, x, y, reps=50, stream=None) -> list:
+    """Average duration (ms) of each kernel pass of one normal apply."""
+    c = _cplx()
+    ms = (ctypes.c_float * 3)()
+    npass = ctypes.c_int()
+    _check(load_library().pfista_profile_normal(
+        plan.handle, _ptr(sens, "sens", c, plan.n_coil), _ptr(mask, "mask", _u8(), plan.mask_numel),
+        _ptr(x, "x", c, plan.n_img), _ptr(y, "y", c, plan.n_img), int(reps), ms, ctypes.byref(npass),
+        _ptr(plan.ws, "ws"), _stream(stream)))
+    return list(ms)[: npass.value]
 
 
 def solve(plan, sens, mask, b, x, lam, degree=3, coef=None, max_iter=50, inv_l=0.0, power_iters=30,

@@ -238,22 +238,36 @@ template <int N_, int T_, int... Rs> struct Plan {
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
 template <int N> struct LdsLen { static constexpr int value = N + N / 16; };
 
+// ------------------------------------------------------------------ twiddles
+// Stage s (with Ns > 1) multiplies input r of butterfly j by
+// exp(-2 pi i r k / (Ns R)), k = j mod Ns.  The plan's table stores these as
+// [stage][k][r-1]: the lanes of one instruction (consecutive k) then read at
+// the odd-ish stride R-1, which spreads them over the LDS banks, and one lane's
+// R-1 factors are contiguous.  Forward sign; the inverse conjugates on use.
+template <class PL> struct TwLayout {
+  static constexpr int off(int s) {
+    int o = 0;
+    for (int i = 0; i < s; ++i)
+      if (PL::ns(i) > 1) o += PL::ns(i) * (PL::R[i] - 1);
+    return o;
+  }
+  static constexpr int size() { return off(PL::NST) > 0 ? off(PL::NST) : 1; }
+};
+
 // ------------------------------------------------------------------ stages
 template <class PL, int S, int DIR>
 __device__ __forceinline__ void stage_compute(float2 *v, int j0, const float2 *tw) {
   constexpr int R = PL::R[S];
   constexpr int NS = PL::ns(S);
   constexpr int NB = PL::nb(S);
-  constexpr int N = PL::N;
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     if constexpr (NS > 1) {
       const int j = j0 + b * PL::T;
-      const int k = j % NS;
-      constexpr int STEP = N / (NS * R);
+      const float2 *tk = tw + TwLayout<PL>::off(S) + (j % NS) * (R - 1);
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        float2 w = tw[r * k * STEP];
+        float2 w = tk[r - 1];
         if (DIR > 0) w.y = -w.y;
         v[b * R + r] = cmul(v[b * R + r], w);
       }
@@ -262,8 +276,23 @@ __device__ __forceinline__ void stage_compute(float2 *v, int j0, const float2 *t
   }
 }
 
-// hand stage S's outputs to stage S+1's inputs through the group's LDS buffer
-template <class PL, int S>
+// Synchronisation of a transform group's LDS hand-over.  WAVE: the group lies
+// inside one wavefront, whose LDS instructions execute in program order, so a
+// compiler-level fence at wavefront scope suffices; otherwise a block barrier.
+template <bool WAVE> __device__ __forceinline__ void group_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+// hand stage S's outputs to stage S+1's inputs through the group's LDS buffer;
+// element i of the group lives at buf[lpad(i) * LS] (LS > 1 interleaves the
+// groups of a wave, which keeps their lanes on distinct banks)
+template <class PL, int S, bool WAVE, int LS>
 __device__ __forceinline__ void stage_exchange(float2 *v, float2 *buf, int j0) {
   constexpr int R = PL::R[S];
   constexpr int NS = PL::ns(S);
@@ -275,10 +304,10 @@ __device__ __forceinline__ void stage_exchange(float2 *v, float2 *buf, int j0) {
     if ((NB * PL::T == B) || j < B) {
       const int base = (j / NS) * NS * R + (j % NS);
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[lpad(base + r * NS)] = v[b * R + r];
+      for (int r = 0; r < R; ++r) buf[lpad(base + r * NS) * LS] = v[b * R + r];
     }
   }
-  __syncthreads();
+  group_sync<WAVE>();
   constexpr int R2 = PL::R[S + 1];
   constexpr int B2 = PL::N / R2;
   constexpr int NB2 = PL::nb(S + 1);
@@ -287,18 +316,19 @@ __device__ __forceinline__ void stage_exchange(float2 *v, float2 *buf, int j0) {
     const int j = j0 + b * PL::T;
     if ((NB2 * PL::T == B2) || j < B2) {
 #pragma unroll
-      for (int r = 0; r < R2; ++r) v[b * R2 + r] = buf[lpad(j + r * B2)];
+      for (int r = 0; r < R2; ++r) v[b * R2 + r] = buf[lpad(j + r * B2) * LS];
     }
   }
-  __syncthreads();
+  group_sync<WAVE>();
 }
 
-template <class PL, int DIR, int S = 0>
+// tw: the plan's twiddle table (TwLayout<PL>), in LDS
+template <class PL, int DIR, int LS = 1, bool WAVE = true, int S = 0>
 __device__ __forceinline__ void fft_run(float2 *v, float2 *buf, int j0, const float2 *tw) {
   stage_compute<PL, S, DIR>(v, j0, tw);
   if constexpr (S + 1 < PL::NST) {
-    stage_exchange<PL, S>(v, buf, j0);
-    fft_run<PL, DIR, S + 1>(v, buf, j0, tw);
+    stage_exchange<PL, S, WAVE, LS>(v, buf, j0);
+    fft_run<PL, DIR, LS, WAVE, S + 1>(v, buf, j0, tw);
   }
 }
 

@@ -20,62 +20,129 @@
 
 namespace pf {
 
-// twiddle tables exp(-2 pi i m / N), m < N, for every supported N, FP64-computed
-// on the host and rounded once to FP32
-constexpr int kTwTotal = 64 + 128 + 160 + 192 + 256 + 320 + 384 + 512;
-__device__ float2 g_tw[kTwTotal];
-
-template <int N> struct TwOff;
-template <> struct TwOff<64> { static constexpr int v = 0; };
-template <> struct TwOff<128> { static constexpr int v = 64; };
-template <> struct TwOff<160> { static constexpr int v = 192; };
-template <> struct TwOff<192> { static constexpr int v = 352; };
-template <> struct TwOff<256> { static constexpr int v = 544; };
-template <> struct TwOff<320> { static constexpr int v = 800; };
-template <> struct TwOff<384> { static constexpr int v = 1120; };
-template <> struct TwOff<512> { static constexpr int v = 1504; };
-
 // forward plan F and its mirror I (inverse); T = lanes per transform
 template <int N> struct Plans;
 template <> struct Plans<64> { using F = Plan<64, 8, 8, 8>; using I = Plan<64, 8, 8, 8>; };
 template <> struct Plans<128> { using F = Plan<128, 8, 16, 8>; using I = Plan<128, 8, 8, 16>; };
 template <> struct Plans<160> { using F = Plan<160, 16, 10, 16>; using I = Plan<160, 16, 16, 10>; };
 template <> struct Plans<192> { using F = Plan<192, 16, 12, 16>; using I = Plan<192, 16, 16, 12>; };
+#ifndef PF_PLAN256
+#define PF_PLAN256 0
+#endif
+#if PF_PLAN256 == 1
+template <> struct Plans<256> { using F = Plan<256, 32, 8, 8, 4>; using I = Plan<256, 32, 4, 8, 8>; };
+#else
 template <> struct Plans<256> { using F = Plan<256, 16, 16, 16>; using I = Plan<256, 16, 16, 16>; };
+#endif
 template <> struct Plans<320> { using F = Plan<320, 16, 20, 4, 4>; using I = Plan<320, 16, 4, 4, 20>; };
 template <> struct Plans<384> { using F = Plan<384, 16, 8, 8, 6>; using I = Plan<384, 16, 6, 8, 8>; };
 template <> struct Plans<512> { using F = Plan<512, 16, 8, 8, 8>; using I = Plan<512, 16, 8, 8, 8>; };
 
-template <int N> struct Geo {
-  using F = typename Plans<N>::F;
-  using I = typename Plans<N>::I;
+// Plans of the one-pass phase-encode operator: fewer values per lane (more
+// lanes per transform) keep its four per-lane arrays within two waves per SIMD.
+template <int N> struct Plans1D { using F = typename Plans<N>::F; using I = typename Plans<N>::I; };
+#ifndef PF_PLAN1D384
+#define PF_PLAN1D384 2
+#endif
+#if PF_PLAN1D384 == 1
+template <> struct Plans1D<384> { using F = Plan<384, 16, 8, 8, 6>; using I = Plan<384, 16, 6, 8, 8>; };
+#elif PF_PLAN1D384 == 2
+template <> struct Plans1D<384> { using F = Plan<384, 32, 12, 8, 4>; using I = Plan<384, 32, 4, 8, 12>; };
+#else
+template <> struct Plans1D<384> { using F = Plan<384, 32, 12, 4, 4, 2>; using I = Plan<384, 32, 2, 4, 4, 12>; };
+#endif
+template <> struct Plans1D<320> { using F = Plan<320, 32, 10, 4, 8>; using I = Plan<320, 32, 8, 4, 10>; };
+template <> struct Plans1D<512> { using F = Plan<512, 32, 16, 4, 8>; using I = Plan<512, 32, 8, 4, 16>; };
+
+template <class F, class I> struct PairGeo {
+  static constexpr int N = F::N;
   static constexpr int T = F::T;
-  static_assert(I::T == T, "mirrored plans share T");
+  static_assert(I::T == T && I::N == N, "mirrored plans share N and T");
   static_assert(I::R_in == F::R_out && I::R_out == F::R_in, "plans must mirror");
   static constexpr int P = F::pmax() > I::pmax() ? F::pmax() : I::pmax();
+  static constexpr int P_IN = F::NB_in * F::R_in;     // == I::NB_out * I::R_out
+  static constexpr int P_OUT = F::NB_out * F::R_out;  // == I::NB_in * I::R_in
+  static_assert(P_IN == I::NB_out * I::R_out && P_OUT == I::NB_in * I::R_in, "layouts must match");
+  static_assert(P_OUT <= 32, "mask bits must fit one word");
   static constexpr int LDSN = LdsLen<N>::value;
-  static constexpr int ROW_THREADS = 256;
-  static constexpr int G = ROW_THREADS / T;   // transforms per row-pass workgroup
-  static constexpr int COLS = 16;             // columns per column-pass workgroup
-  static constexpr int COL_THREADS = COLS * T;
+  static constexpr int THREADS = 256;
+  static constexpr int G = THREADS / T;   // transforms per workgroup
+  static constexpr int CPW = 64 / T;      // columns per wave in column kernels
+  static constexpr int COLS = 4 * CPW;    // columns per column-kernel workgroup
+};
+template <int N> struct Geo : PairGeo<typename Plans<N>::F, typename Plans<N>::I> {
+  using F = typename Plans<N>::F;
+  using I = typename Plans<N>::I;
+};
+template <int N> struct Geo1D : PairGeo<typename Plans1D<N>::F, typename Plans1D<N>::I> {
+  using F = typename Plans1D<N>::F;
+  using I = typename Plans1D<N>::I;
 };
 
-template <int N> __device__ __forceinline__ void load_twiddles(float2 *s_tw) {
-  for (int i = threadIdx.x; i < N; i += blockDim.x) s_tw[i] = g_tw[TwOff<N>::v + i];
+// Twiddle tables of every plan (TwLayout order), FP64-computed on the host and
+// rounded once to FP32; per image side N: [F][I][F 1-D][I 1-D].
+template <int N> struct TwBlock {
+  static constexpr int f = 0;
+  static constexpr int i = f + TwLayout<typename Plans<N>::F>::size();
+  static constexpr int f1 = i + TwLayout<typename Plans<N>::I>::size();
+  static constexpr int i1 = f1 + TwLayout<typename Plans1D<N>::F>::size();
+  static constexpr int size = i1 + TwLayout<typename Plans1D<N>::I>::size();
+};
+template <int N> struct TwBase;
+template <> struct TwBase<64> { static constexpr int v = 0; };
+template <> struct TwBase<128> { static constexpr int v = TwBase<64>::v + TwBlock<64>::size; };
+template <> struct TwBase<160> { static constexpr int v = TwBase<128>::v + TwBlock<128>::size; };
+template <> struct TwBase<192> { static constexpr int v = TwBase<160>::v + TwBlock<160>::size; };
+template <> struct TwBase<256> { static constexpr int v = TwBase<192>::v + TwBlock<192>::size; };
+template <> struct TwBase<320> { static constexpr int v = TwBase<256>::v + TwBlock<256>::size; };
+template <> struct TwBase<384> { static constexpr int v = TwBase<320>::v + TwBlock<320>::size; };
+template <> struct TwBase<512> { static constexpr int v = TwBase<384>::v + TwBlock<384>::size; };
+constexpr int kTwTotal = TwBase<512>::v + TwBlock<512>::size;
+__device__ float2 g_tw[kTwTotal];
+
+// copy `count` table entries starting at `off` into LDS (block-strided)
+__device__ __forceinline__ void load_tw(float2 *dst, int off, int count) {
+  for (int i = threadIdx.x; i < count; i += blockDim.x) dst[i] = g_tw[off + i];
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+  for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+
+// Opaque copy of a lane index: keeps the compiler from hoisting every per-lane
+// twiddle and LDS index of a transform out of a coil loop (which would pin them
+// in registers for the whole loop); they are recomputed each iteration instead.
+__device__ __forceinline__ int opaque(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
+// register layouts: "in" = F's first stage = I's last stage; "out" = F's last = I's first
+template <class PL> __device__ __forceinline__ bool lay_in_ok(int j) {
+  return (PL::NB_in * PL::T == PL::B_in) || j < PL::B_in;
+}
+template <class PL> __device__ __forceinline__ bool lay_out_ok(int j) {
+  return (PL::NB_out * PL::T == PL::B_out) || j < PL::B_out;
 }
 
 // ---------------------------------------------------------------------------
-// Pass 1: t_c[s, y, :] = DFT_x(S_c[s, y, :] * x[s, y, :]); task = (s, y, c), c fastest
+// Pass 1: t_c[s, y, :] = DFT_x(S_c[s, y, :] * x[s, y, :]); task = (s, y, c), c fastest.
+// A transform group is T consecutive lanes of one wave (wave-level hand-over).
 template <int N>
 __global__ __launch_bounds__(256) void k_row_fwd(const float2 *__restrict__ x,
                                                  const float2 *__restrict__ sens,
-                                                 float2 *__restrict__ t, int C, int tasks) {
+                                                 float2 *__restrict__ t, int C, int tasks,
+                                                 int *k_inc) {
   using Gm = Geo<N>;
   using F = typename Gm::F;
+  // the solver's iteration counter: advanced here, read by the step kernel of
+  // the same iteration (stream order separates the two)
+  if (k_inc && blockIdx.x == 0 && threadIdx.x == 0) *k_inc += 1;
   constexpr int T = Gm::T;
-  __shared__ float2 s_tw[N];
+  __shared__ float2 s_tw[TwLayout<F>::size()];
   __shared__ float2 s_buf[Gm::G][Gm::LDSN];
-  load_twiddles<N>(s_tw);
   const int g = threadIdx.x / T, j0 = threadIdx.x % T;
   const int task = blockIdx.x * Gm::G + g;
   const bool valid = task < tasks;
@@ -88,20 +155,21 @@ __global__ __launch_bounds__(256) void k_row_fwd(const float2 *__restrict__ x,
 #pragma unroll
   for (int b = 0; b < F::NB_in; ++b) {
     const int j = j0 + b * T;
-    const bool ok = valid && ((F::NB_in * T == F::B_in) || j < F::B_in);
+    const bool ok = valid && lay_in_ok<F>(j);
 #pragma unroll
     for (int r = 0; r < F::R_in; ++r) {
       const int i = j + r * F::B_in;
       v[b * F::R_in + r] = ok ? cmul(sr[i], xr[i]) : make_float2(0.f, 0.f);
     }
   }
+  load_tw(s_tw, TwBase<N>::v + TwBlock<N>::f, TwLayout<F>::size());
   __syncthreads();
   fft_run<F, -1>(v, s_buf[g], j0, s_tw);
   float2 *tr = t + ((size_t)(s * C + c) * N + yy) * N;
 #pragma unroll
   for (int b = 0; b < F::NB_out; ++b) {
     const int j = j0 + b * T;
-    if (valid && ((F::NB_out * T == F::B_out) || j < F::B_out)) {
+    if (valid && lay_out_ok<F>(j)) {
 #pragma unroll
       for (int r = 0; r < F::R_out; ++r) tr[j + r * F::B_out] = v[b * F::R_out + r];
     }
@@ -109,7 +177,8 @@ __global__ __launch_bounds__(256) void k_row_fwd(const float2 *__restrict__ x,
 }
 
 // ---------------------------------------------------------------------------
-// Pass 2 (columns).  Block = 16 adjacent columns k of one (s, c); lane = col + 16 j0.
+// Pass 2 (columns).  Block = COLS adjacent columns k of one (s, c); wave w owns
+// columns w*CPW .. w*CPW+CPW-1, lane = column + CPW * j0 inside the wave.
 enum ColMode { COL_NORMAL = 0, COL_FWD_OUT = 1, COL_ADJ_IN = 2, COL_RESID = 3 };
 
 template <int MASK1D> __device__ __forceinline__ bool sampled(const uint8_t *mask_s, int ky, int kx, int N) {
@@ -117,21 +186,22 @@ template <int MASK1D> __device__ __forceinline__ bool sampled(const uint8_t *mas
 }
 
 template <int N, int MODE, int MASK1D>
-__global__ __launch_bounds__(Geo<N>::COL_THREADS) void k_col(float2 *__restrict__ t,
-                                                             const float2 *__restrict__ kin,
-                                                             float2 *__restrict__ kout,
-                                                             const uint8_t *__restrict__ mask, int C,
-                                                             float a_scale, float b_scale,
-                                                             double *__restrict__ partials) {
+__global__ __launch_bounds__(256, 2) void k_col(float2 *__restrict__ t, const float2 *__restrict__ kin,
+                                             float2 *__restrict__ kout, const uint8_t *__restrict__ mask,
+                                             int C, float a_scale, float b_scale,
+                                             double *__restrict__ partials) {
   using Gm = Geo<N>;
   using F = typename Gm::F;
   using I = typename Gm::I;
   constexpr int T = Gm::T;
-  __shared__ float2 s_tw[N];
-  __shared__ float2 s_buf[Gm::COLS][Gm::LDSN];
-  __shared__ double s_red[Gm::COL_THREADS];
-  load_twiddles<N>(s_tw);
-  const int col = threadIdx.x % Gm::COLS, j0 = threadIdx.x / Gm::COLS;
+  __shared__ float2 s_twF[TwLayout<F>::size()];
+  __shared__ float2 s_twI[TwLayout<I>::size()];
+  __shared__ float2 s_buf[Gm::COLS * Gm::LDSN];
+  __shared__ double s_red[4];
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  const int ci = ln % Gm::CPW, col = wv * Gm::CPW + ci, j0 = ln / Gm::CPW;
+  // this column's exchange buffer: the wave's columns interleaved element by element
+  float2 *bufc = s_buf + wv * Gm::CPW * Gm::LDSN + ci;
   const int kx = blockIdx.x * Gm::COLS + col;
   const int sc = blockIdx.y;
   const int s = sc / C;
@@ -140,44 +210,53 @@ __global__ __launch_bounds__(Geo<N>::COL_THREADS) void k_col(float2 *__restrict_
   float2 v[Gm::P];
   double acc = 0.0;
 
+  // sampling flags at the k-space positions this lane holds (F's output layout)
+  unsigned mbits = 0;
+#pragma unroll
+  for (int b = 0; b < F::NB_out; ++b) {
+    const int j = j0 + b * T;
+#pragma unroll
+    for (int r = 0; r < F::R_out; ++r)
+      if (lay_out_ok<F>(j) && sampled<MASK1D>(mask_s, j + r * F::B_out, kx, N)) mbits |= 1u << (b * F::R_out + r);
+  }
+
   if constexpr (MODE == COL_ADJ_IN) {
-    // v = M b (masked k-space input) laid out as the inverse's inputs
     const float2 *kc = kin + (size_t)sc * N * N;
 #pragma unroll
     for (int b = 0; b < I::NB_in; ++b) {
       const int j = j0 + b * T;
-      const bool ok = (I::NB_in * T == I::B_in) || j < I::B_in;
 #pragma unroll
       for (int r = 0; r < I::R_in; ++r) {
         const int ky = j + r * I::B_in;
-        v[b * I::R_in + r] = (ok && sampled<MASK1D>(mask_s, ky, kx, N)) ? kc[(size_t)ky * N + kx]
-                                                                         : make_float2(0.f, 0.f);
+        v[b * I::R_in + r] = ((mbits >> (b * I::R_in + r)) & 1u) ? kc[(size_t)ky * N + kx] : make_float2(0.f, 0.f);
       }
     }
+    load_tw(s_twI, TwBase<N>::v + TwBlock<N>::i, TwLayout<I>::size());
     __syncthreads();
   } else {
 #pragma unroll
     for (int b = 0; b < F::NB_in; ++b) {
       const int j = j0 + b * T;
-      const bool ok = (F::NB_in * T == F::B_in) || j < F::B_in;
+      const bool ok = lay_in_ok<F>(j);
 #pragma unroll
       for (int r = 0; r < F::R_in; ++r) {
         const int yy = j + r * F::B_in;
         v[b * F::R_in + r] = ok ? tc[(size_t)yy * N + kx] : make_float2(0.f, 0.f);
       }
     }
+    load_tw(s_twF, TwBase<N>::v + TwBlock<N>::f, TwLayout<F>::size());
+    if constexpr (MODE == COL_NORMAL) load_tw(s_twI, TwBase<N>::v + TwBlock<N>::i, TwLayout<I>::size());
     __syncthreads();
-    fft_run<F, -1>(v, s_buf[col], j0, s_tw);
-    // registers now hold X[ky] for ky = j + r * F::B_out
+    fft_run<F, -1, Gm::CPW>(v, bufc, j0, s_twF);
 #pragma unroll
     for (int b = 0; b < F::NB_out; ++b) {
       const int j = j0 + b * T;
-      const bool ok = (F::NB_out * T == F::B_out) || j < F::B_out;
+      const bool ok = lay_out_ok<F>(j);
 #pragma unroll
       for (int r = 0; r < F::R_out; ++r) {
         const int ky = j + r * F::B_out;
         float2 &e = v[b * F::R_out + r];
-        const bool m = ok && sampled<MASK1D>(mask_s, ky, kx, N);
+        const bool m = (mbits >> (b * F::R_out + r)) & 1u;
         if constexpr (MODE == COL_NORMAL) {
           if (!m) e = make_float2(0.f, 0.f);
         } else if constexpr (MODE == COL_FWD_OUT) {
@@ -195,11 +274,11 @@ __global__ __launch_bounds__(Geo<N>::COL_THREADS) void k_col(float2 *__restrict_
   }
 
   if constexpr (MODE == COL_NORMAL || MODE == COL_ADJ_IN) {
-    fft_run<I, +1>(v, s_buf[col], j0, s_tw);
+    fft_run<I, +1, Gm::CPW>(v, bufc, j0, s_twI);
 #pragma unroll
     for (int b = 0; b < I::NB_out; ++b) {
       const int j = j0 + b * T;
-      if ((I::NB_out * T == I::B_out) || j < I::B_out) {
+      if (lay_out_ok<I>(j)) {
 #pragma unroll
         for (int r = 0; r < I::R_out; ++r) tc[(size_t)(j + r * I::B_out) * N + kx] = v[b * I::R_out + r];
       }
@@ -207,23 +286,21 @@ __global__ __launch_bounds__(Geo<N>::COL_THREADS) void k_col(float2 *__restrict_
   }
 
   if constexpr (MODE == COL_RESID) {
-    // deterministic block sum of the FP64 partials
-    s_red[threadIdx.x] = acc;
+    // deterministic block sum of the FP64 partials: wave sums, then waves in order
+    acc = wave_sum_d(acc);
+    if (ln == 0) s_red[wv] = acc;
     __syncthreads();
-    for (int h = Gm::COL_THREADS / 2; h > 0; h >>= 1) {
-      if (threadIdx.x < h) s_red[threadIdx.x] += s_red[threadIdx.x + h];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) partials[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = s_red[0];
+    if (threadIdx.x == 0)
+      partials[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = ((s_red[0] + s_red[1]) + s_red[2]) + s_red[3];
   }
 }
 
 // ---------------------------------------------------------------------------
 // Pass 3: y[s, r, :] = alpha sum_c conj(S_c[s, r, :]) IDFT_x(t_c[s, r, :]) + beta w.
-// Block = RPW rows; transform group g handles row (g % RPW) and coils
-// g / RPW, g / RPW + G / RPW, ...; groups are summed in a fixed order.
+// Block = rpw rows; transform group g handles row (g % rpw) and coils
+// g / rpw, g / rpw + G / rpw, ...; the groups are summed in a fixed order.
 template <int N>
-__global__ __launch_bounds__(256) void k_row_inv(const float2 *__restrict__ t,
+__global__ __launch_bounds__(256, 2) void k_row_inv(const float2 *__restrict__ t,
                                                  const float2 *__restrict__ sens,
                                                  float2 *__restrict__ y, const float2 *w, float alpha,
                                                  float beta, int C, int rows, int rpw) {
@@ -231,50 +308,53 @@ __global__ __launch_bounds__(256) void k_row_inv(const float2 *__restrict__ t,
   using I = typename Gm::I;
   constexpr int T = Gm::T;
   constexpr int G = Gm::G;
-  __shared__ float2 s_tw[N];
+  __shared__ float2 s_tw[TwLayout<I>::size()];
   __shared__ float2 s_buf[G][Gm::LDSN];
-  load_twiddles<N>(s_tw);
   const int g = threadIdx.x / T, j0 = threadIdx.x % T;
   const int ro = g % rpw, cg = g / rpw, cstep = G / rpw;
   const int row = blockIdx.x * rpw + ro;
   const bool rvalid = row < rows;
   const int s = rvalid ? row / N : 0, yy = rvalid ? row % N : 0;
-  float2 acc[Gm::P];
+  float2 acc[Gm::P_IN];
 #pragma unroll
-  for (int i = 0; i < Gm::P; ++i) acc[i] = make_float2(0.f, 0.f);
+  for (int i = 0; i < Gm::P_IN; ++i) acc[i] = make_float2(0.f, 0.f);
   const int iters = (C + cstep - 1) / cstep;
   for (int it = 0; it < iters; ++it) {
     const int c = cg + it * cstep;
     const bool valid = rvalid && c < C;
     const size_t off = ((size_t)(s * C + (valid ? c : 0)) * N + yy) * N;
     const float2 *tr = t + off;
-    float2 v[Gm::P];
+    const float2 *sr = sens + off;
+    float2 v[Gm::P], sv[Gm::P_IN];
 #pragma unroll
     for (int b = 0; b < I::NB_in; ++b) {
       const int j = j0 + b * T;
-      const bool ok = valid && ((I::NB_in * T == I::B_in) || j < I::B_in);
+      const bool ok = valid && lay_in_ok<I>(j);
 #pragma unroll
       for (int r = 0; r < I::R_in; ++r) v[b * I::R_in + r] = ok ? tr[j + r * I::B_in] : make_float2(0.f, 0.f);
     }
-    fft_run<I, +1>(v, s_buf[g], j0, s_tw);
-    const float2 *sr = sens + off;
 #pragma unroll
     for (int b = 0; b < I::NB_out; ++b) {
       const int j = j0 + b * T;
-      const bool ok = valid && ((I::NB_out * T == I::B_out) || j < I::B_out);
+      const bool ok = valid && lay_out_ok<I>(j);
 #pragma unroll
-      for (int r = 0; r < I::R_out; ++r) {
-        if (ok) acc[b * I::R_out + r] = cadd(acc[b * I::R_out + r], cmulc(v[b * I::R_out + r], sr[j + r * I::B_out]));
-      }
+      for (int r = 0; r < I::R_out; ++r) sv[b * I::R_out + r] = ok ? sr[j + r * I::B_out] : make_float2(0.f, 0.f);
     }
-    __syncthreads();
+    if (it == 0) {
+      load_tw(s_tw, TwBase<N>::v + TwBlock<N>::i, TwLayout<I>::size());
+      __syncthreads();
+    }
+    fft_run<I, +1>(v, s_buf[opaque(g)], opaque(j0), s_tw);
+#pragma unroll
+    for (int i = 0; i < Gm::P_IN; ++i) acc[i] = cadd(acc[i], cmulc(v[i], sv[i]));
   }
+  __syncthreads();
   // partial sums per group -> LDS (natural order), then fixed-order sum over coil groups
   float2 *red = &s_buf[0][0];
 #pragma unroll
   for (int b = 0; b < I::NB_out; ++b) {
     const int j = j0 + b * T;
-    if ((I::NB_out * T == I::B_out) || j < I::B_out) {
+    if (lay_out_ok<I>(j)) {
 #pragma unroll
       for (int r = 0; r < I::R_out; ++r) red[g * N + j + r * I::B_out] = acc[b * I::R_out + r];
     }
@@ -294,92 +374,229 @@ __global__ __launch_bounds__(256) void k_row_inv(const float2 *__restrict__ t,
 }
 
 // ---------------------------------------------------------------------------
-// One-pass normal operator for a phase-encode mask (sampled rows ky, all kx):
-// F^H M F = (F_y^H M_y F_y) (x) I, so each column only needs a y transform pair.
-// Block = 16 columns of one slice, all coils accumulated in registers.
+// Pass 3 of one apply fused with pass 1 of the next (the Horner chain feeds each
+// output straight back in): for every row r
+//   y[s, r, :] = alpha sum_c conj(S_c) IDFT_x(t_c[s, r, :]) + beta w[s, r, :]
+//   t_c[s, r, :] = DFT_x(S_c[s, r, :] y[s, r, :])            (in place)
+// The row's coil maps are read once for both halves.
 template <int N>
-__global__ __launch_bounds__(Geo<N>::COL_THREADS) void k_normal_1d(const float2 *__restrict__ x,
-                                                                   const float2 *__restrict__ sens,
-                                                                   const uint8_t *__restrict__ mask,
-                                                                   float2 *__restrict__ y,
-                                                                   const float2 *w, float alpha,
-                                                                   float beta, int C) {
+__global__ __launch_bounds__(256, 2) void k_row_inv_fwd(float2 *__restrict__ t, const float2 *__restrict__ sens,
+                                                        float2 *__restrict__ y, const float2 *w, float alpha,
+                                                        float beta, int C, int rows, int rpw) {
   using Gm = Geo<N>;
   using F = typename Gm::F;
   using I = typename Gm::I;
   constexpr int T = Gm::T;
-  __shared__ float2 s_tw[N];
-  __shared__ float2 s_buf[Gm::COLS][Gm::LDSN];
-  load_twiddles<N>(s_tw);
-  const int col = threadIdx.x % Gm::COLS, j0 = threadIdx.x / Gm::COLS;
+  constexpr int G = Gm::G;
+  static_assert(Gm::P_IN == F::NB_in * F::R_in, "layouts");
+  __shared__ float2 s_twF[TwLayout<F>::size()];
+  __shared__ float2 s_twI[TwLayout<I>::size()];
+  __shared__ float2 s_buf[G][Gm::LDSN];
+  const int g = threadIdx.x / T, j0 = threadIdx.x % T;
+  const int ro = g % rpw, cg = g / rpw, cstep = G / rpw;
+  const int row = blockIdx.x * rpw + ro;
+  const bool rvalid = row < rows;
+  const int s = rvalid ? row / N : 0, yy = rvalid ? row % N : 0;
+  float2 acc[Gm::P_IN], sv[Gm::P_IN];
+#pragma unroll
+  for (int i = 0; i < Gm::P_IN; ++i) acc[i] = make_float2(0.f, 0.f);
+  const int iters = (C + cstep - 1) / cstep;
+  for (int it = 0; it < iters; ++it) {
+    const int c = cg + it * cstep;
+    const bool valid = rvalid && c < C;
+    const size_t off = ((size_t)(s * C + (valid ? c : 0)) * N + yy) * N;
+    const float2 *tr = t + off;
+    const float2 *sr = sens + off;
+    float2 v[Gm::P];
+#pragma unroll
+    for (int b = 0; b < I::NB_in; ++b) {
+      const int j = j0 + b * T;
+      const bool ok = valid && lay_in_ok<I>(j);
+#pragma unroll
+      for (int r = 0; r < I::R_in; ++r) v[b * I::R_in + r] = ok ? tr[j + r * I::B_in] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int b = 0; b < I::NB_out; ++b) {
+      const int j = j0 + b * T;
+      const bool ok = valid && lay_out_ok<I>(j);
+#pragma unroll
+      for (int r = 0; r < I::R_out; ++r) sv[b * I::R_out + r] = ok ? sr[j + r * I::B_out] : make_float2(0.f, 0.f);
+    }
+    if (it == 0) {
+      load_tw(s_twI, TwBase<N>::v + TwBlock<N>::i, TwLayout<I>::size());
+      load_tw(s_twF, TwBase<N>::v + TwBlock<N>::f, TwLayout<F>::size());
+      __syncthreads();
+    }
+    fft_run<I, +1>(v, s_buf[opaque(g)], opaque(j0), s_twI);
+#pragma unroll
+    for (int i = 0; i < Gm::P_IN; ++i) acc[i] = cadd(acc[i], cmulc(v[i], sv[i]));
+  }
+  __syncthreads();
+  float2 *red = &s_buf[0][0];
+#pragma unroll
+  for (int b = 0; b < I::NB_out; ++b) {
+    const int j = j0 + b * T;
+    if (lay_out_ok<I>(j)) {
+#pragma unroll
+      for (int r = 0; r < I::R_out; ++r) red[g * N + j + r * I::B_out] = acc[b * I::R_out + r];
+    }
+  }
+  __syncthreads();
+  // combined rows: written out, and kept in the q = 0 slot of each row for the forward half
+  for (int e = threadIdx.x; e < rpw * N; e += blockDim.x) {
+    const int r_o = e / N, i = e % N;
+    const int rr = blockIdx.x * rpw + r_o;
+    float2 sum = red[r_o * N + i];
+    for (int q = 1; q < cstep; ++q) sum = cadd(sum, red[(q * rpw + r_o) * N + i]);
+    float2 out = cscale(sum, alpha);
+    if (rr < rows) {
+      const size_t o = (size_t)rr * N + i;
+      if (w) out = cadd(out, cscale(w[o], beta));
+      y[o] = out;
+    }
+    red[r_o * N + i] = out;
+  }
+  __syncthreads();
+  float2 yv[Gm::P_IN];
+#pragma unroll
+  for (int b = 0; b < F::NB_in; ++b) {
+    const int j = j0 + b * T;
+#pragma unroll
+    for (int r = 0; r < F::R_in; ++r) yv[b * F::R_in + r] = lay_in_ok<F>(j) ? red[ro * N + j + r * F::B_in] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  for (int it = 0; it < iters; ++it) {
+    const int c = cg + it * cstep;
+    const bool valid = rvalid && c < C;
+    const size_t off = ((size_t)(s * C + (valid ? c : 0)) * N + yy) * N;
+    if (iters > 1) {
+      const float2 *sr = sens + off;
+#pragma unroll
+      for (int b = 0; b < F::NB_in; ++b) {
+        const int j = j0 + b * T;
+        const bool ok = valid && lay_in_ok<F>(j);
+#pragma unroll
+        for (int r = 0; r < F::R_in; ++r) sv[b * F::R_in + r] = ok ? sr[j + r * F::B_in] : make_float2(0.f, 0.f);
+      }
+    }
+    float2 v[Gm::P];
+#pragma unroll
+    for (int i = 0; i < Gm::P_IN; ++i) v[i] = cmul(sv[i], yv[i]);
+    fft_run<F, -1>(v, s_buf[opaque(g)], opaque(j0), s_twF);
+    float2 *tr = t + off;
+#pragma unroll
+    for (int b = 0; b < F::NB_out; ++b) {
+      const int j = j0 + b * T;
+      if (valid && lay_out_ok<F>(j)) {
+#pragma unroll
+        for (int r = 0; r < F::R_out; ++r) tr[j + r * F::B_out] = v[b * F::R_out + r];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One-pass normal operator for a phase-encode mask (sampled rows ky, all kx):
+// F^H M F = (F_y^H M_y F_y) (x) I, so each column only needs a y transform pair.
+// Block = COLS columns of one slice, wave-private transform groups; all coils
+// are accumulated in registers, the next coil map is prefetched while the
+// current one is transformed.
+#ifndef PF_1D_WAVES
+#define PF_1D_WAVES 2
+#endif
+#ifndef PF_1D_PREFETCH
+#define PF_1D_PREFETCH 0
+#endif
+template <int N>
+__global__ __launch_bounds__(256, PF_1D_WAVES) void k_normal_1d(const float2 *__restrict__ x,
+                                                   const float2 *__restrict__ sens,
+                                                   const uint8_t *__restrict__ mask,
+                                                   float2 *__restrict__ y, const float2 *w, float alpha,
+                                                   float beta, int C, int *k_inc) {
+  using Gm = Geo1D<N>;
+  if (k_inc && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *k_inc += 1;
+  using F = typename Gm::F;
+  using I = typename Gm::I;
+  constexpr int T = Gm::T;
+  constexpr int PI = Gm::P_IN;
+  __shared__ float2 s_twF[TwLayout<F>::size()];
+  __shared__ float2 s_twI[TwLayout<I>::size()];
+  __shared__ float2 s_buf[Gm::COLS * Gm::LDSN];
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  const int ci = ln % Gm::CPW, col = wv * Gm::CPW + ci, j0 = ln / Gm::CPW;
   const int kx = blockIdx.x * Gm::COLS + col;
   const int s = blockIdx.y;
   const uint8_t *mask_s = mask + (size_t)s * N;
   const float2 *xs = x + (size_t)s * N * N;
-  // F's input layout == I's output layout: positions yy = j + r * F::B_in
-  float2 xv[Gm::P], acc[Gm::P];
+  const float2 *ss = sens + (size_t)s * C * N * N;
+  // positions yy = j + r * F::B_in (F input layout == I output layout)
+  auto pos = [&](int i) { return (j0 + (i / F::R_in) * T + (i % F::R_in) * F::B_in) * N + kx; };
+  auto okp = [&](int i) { return lay_in_ok<F>(j0 + (i / F::R_in) * T); };
+  unsigned mbits = 0;
 #pragma unroll
-  for (int b = 0; b < F::NB_in; ++b) {
+  for (int b = 0; b < F::NB_out; ++b) {
     const int j = j0 + b * T;
-    const bool ok = (F::NB_in * T == F::B_in) || j < F::B_in;
 #pragma unroll
-    for (int r = 0; r < F::R_in; ++r) {
-      xv[b * F::R_in + r] = ok ? xs[(size_t)(j + r * F::B_in) * N + kx] : make_float2(0.f, 0.f);
-      acc[b * F::R_in + r] = make_float2(0.f, 0.f);
-    }
+    for (int r = 0; r < F::R_out; ++r)
+      if (lay_out_ok<F>(j) && mask_s[j + r * F::B_out] != 0) mbits |= 1u << (b * F::R_out + r);
   }
+  float2 xv[PI], acc[PI], sc[PI];
+#pragma unroll
+  for (int i = 0; i < PI; ++i) {
+    xv[i] = okp(i) ? xs[pos(i)] : make_float2(0.f, 0.f);
+    sc[i] = okp(i) ? ss[pos(i)] : make_float2(0.f, 0.f);
+    acc[i] = make_float2(0.f, 0.f);
+  }
+  load_tw(s_twF, TwBase<N>::v + TwBlock<N>::f1, TwLayout<F>::size());
+  load_tw(s_twI, TwBase<N>::v + TwBlock<N>::i1, TwLayout<I>::size());
   __syncthreads();
   for (int c = 0; c < C; ++c) {
-    const float2 *sc = sens + (size_t)(s * C + c) * N * N;
-    float2 v[Gm::P];
+    float2 v[Gm::P], sn[PI];
 #pragma unroll
-    for (int b = 0; b < F::NB_in; ++b) {
-      const int j = j0 + b * T;
-      const bool ok = (F::NB_in * T == F::B_in) || j < F::B_in;
+    for (int i = 0; i < PI; ++i) v[i] = cmul(sc[i], xv[i]);
+    const int jl = opaque(j0);
+    float2 *bl = s_buf + wv * Gm::CPW * Gm::LDSN + opaque(ci);
+#if PF_1D_PREFETCH
+    const float2 *snp = ss + (size_t)(c + 1 < C ? c + 1 : c) * N * N;
+    {
+      const int kxl = opaque(kx);
 #pragma unroll
-      for (int r = 0; r < F::R_in; ++r)
-        v[b * F::R_in + r] = ok ? cmul(sc[(size_t)(j + r * F::B_in) * N + kx], xv[b * F::R_in + r])
-                                : make_float2(0.f, 0.f);
-    }
-    fft_run<F, -1>(v, s_buf[col], j0, s_tw);
-#pragma unroll
-    for (int b = 0; b < F::NB_out; ++b) {
-      const int j = j0 + b * T;
-#pragma unroll
-      for (int r = 0; r < F::R_out; ++r) {
-        const int ky = j + r * F::B_out;
-        if (!(((F::NB_out * T == F::B_out) || j < F::B_out) && mask_s[ky] != 0))
-          v[b * F::R_out + r] = make_float2(0.f, 0.f);
+      for (int i = 0; i < PI; ++i) {
+        const int o = (jl + (i / F::R_in) * T + (i % F::R_in) * F::B_in) * N + kxl;
+        sn[i] = okp(i) ? snp[o] : make_float2(0.f, 0.f);
       }
     }
-    fft_run<I, +1>(v, s_buf[col], j0, s_tw);
+#endif
+    fft_run<F, -1, Gm::CPW>(v, bl, jl, s_twF);
 #pragma unroll
-    for (int b = 0; b < I::NB_out; ++b) {
-      const int j = j0 + b * T;
-      const bool ok = (I::NB_out * T == I::B_out) || j < I::B_out;
+    for (int i = 0; i < Gm::P_OUT; ++i)
+      if (!((mbits >> i) & 1u)) v[i] = make_float2(0.f, 0.f);
+    fft_run<I, +1, Gm::CPW>(v, bl, jl, s_twI);
 #pragma unroll
-      for (int r = 0; r < I::R_out; ++r) {
-        if (ok) {
-          const float2 sv = sc[(size_t)(j + r * I::B_out) * N + kx];
-          acc[b * I::R_out + r] = cadd(acc[b * I::R_out + r], cmulc(v[b * I::R_out + r], sv));
-        }
+    for (int i = 0; i < PI; ++i) acc[i] = cadd(acc[i], cmulc(v[i], sc[i]));
+#if PF_1D_PREFETCH
+#pragma unroll
+    for (int i = 0; i < PI; ++i) sc[i] = sn[i];
+#else
+    if (c + 1 < C) {
+      const float2 *snp = ss + (size_t)(c + 1) * N * N;
+      const int kxl = opaque(kx);
+#pragma unroll
+      for (int i = 0; i < PI; ++i) {
+        const int o = (jl + (i / F::R_in) * T + (i % F::R_in) * F::B_in) * N + kxl;
+        sc[i] = okp(i) ? snp[o] : make_float2(0.f, 0.f);
       }
     }
-    __syncthreads();
+#endif
   }
   float2 *ys = y + (size_t)s * N * N;
   const float2 *ws = w ? w + (size_t)s * N * N : nullptr;
 #pragma unroll
-  for (int b = 0; b < I::NB_out; ++b) {
-    const int j = j0 + b * T;
-    if ((I::NB_out * T == I::B_out) || j < I::B_out) {
-#pragma unroll
-      for (int r = 0; r < I::R_out; ++r) {
-        const size_t o = (size_t)(j + r * I::B_out) * N + kx;
-        float2 out = cscale(acc[b * I::R_out + r], alpha);
-        if (ws) out = cadd(out, cscale(ws[o], beta));
-        ys[o] = out;
-      }
+  for (int i = 0; i < PI; ++i) {
+    if (okp(i)) {
+      float2 out = cscale(acc[i], alpha);
+      if (ws) out = cadd(out, cscale(ws[pos(i)], beta));
+      ys[pos(i)] = out;
     }
   }
 }
@@ -392,14 +609,16 @@ __global__ __launch_bounds__(Geo<N>::COL_THREADS) void k_normal_1d(const float2 
 // Level 1 is in registers; level l >= 2 combines the 2 x 2 lane neighbourhood of
 // stride 2^(l-2) by lane shuffles (every lane of a group computes the same
 // coefficients, so the inverse is again local).
-__device__ __forceinline__ float2 soft_thr(float2 w, float lam, double &l1) {
-  const float m = sqrtf(w.x * w.x + w.y * w.y);
-  if (m > lam) {
-    const float sc = 1.0f - lam / m;
-    l1 += (double)m - (double)lam;
-    return make_float2(w.x * sc, w.y * sc);
-  }
-  return make_float2(0.f, 0.f);
+// Complex soft-threshold, branch-free: keep |w| > lam as |w|^2 > lam^2 and scale
+// by 1 - lam / |w| with the hardware reciprocal square root (about 1 ulp); adds
+// |soft(w)| = |w| - lam to l1.  w = 0 gives exactly 0 for any lam >= 0.
+__device__ __forceinline__ float2 soft_thr(float2 w, float lam, float &l1) {
+  const float m2 = w.x * w.x + w.y * w.y;
+  const bool keep = m2 > lam * lam;
+  const float r = __builtin_amdgcn_rsqf(keep ? m2 : 1.0f);
+  const float sc = keep ? 1.0f - lam * r : 0.0f;
+  l1 += keep ? m2 * r - lam : 0.0f;
+  return make_float2(w.x * sc, w.y * sc);
 }
 
 __device__ __forceinline__ float2 shfl_xor2(float2 v, int m) {
@@ -431,21 +650,55 @@ __device__ __forceinline__ void ihaar4(const Quad &q, float2 &a, float2 &b, floa
   d = cscale(csub(d1, d2), 0.5f);   // ll - dx - dy + dd
 }
 
+// Levels l >= 2 of the Haar prox, one lane group of stride 2^(l-2) at a time:
+// gather the group's four LL values, threshold its three detail coefficients
+// (and the final LL at the last level), recurse to the next level, then invert
+// this level and keep the value at this lane's position.  Compile-time recursion
+// keeps every coefficient in registers.
+__device__ __forceinline__ float2 pick4(int bx, int by, float2 a, float2 b, float2 c, float2 d) {
+  const float2 top = bx ? b : a, bot = bx ? d : c;
+  return by ? bot : top;
+}
+
+template <int L, int LEVELS>
+__device__ __forceinline__ float2 haar_levels(float2 ll, int tx, int ty, float lam, float &l1) {
+  if constexpr (L > LEVELS) {
+    return ll;
+  } else {
+    constexpr int st = 1 << (L - 2);
+    const int bx = (tx >> (L - 2)) & 1, by = (ty >> (L - 2)) & 1;
+    const float2 ox = shfl_xor2(ll, st), oy = shfl_xor2(ll, 8 * st), od = shfl_xor2(ll, 9 * st);
+    // the group's 2 x 2 block [[A, B], [C, D]] seen from this lane's corner
+    const float2 A = pick4(bx, by, ll, ox, oy, od);
+    const float2 B = pick4(bx, by, ox, ll, od, oy);
+    const float2 Cc = pick4(bx, by, oy, od, ll, ox);
+    const float2 D = pick4(bx, by, od, oy, ox, ll);
+    Quad r = haar4(A, B, Cc, D);
+    float l1g = 0.f;   // identical in the four lanes of the group: count it once
+    r.dx = soft_thr(r.dx, lam, l1g);
+    r.dy = soft_thr(r.dy, lam, l1g);
+    r.dd = soft_thr(r.dd, lam, l1g);
+    if constexpr (L == LEVELS) r.ll = soft_thr(r.ll, lam, l1g);
+    if (!(tx & (2 * st - 1)) && !(ty & (2 * st - 1))) l1 += l1g;
+    r.ll = haar_levels<L + 1, LEVELS>(r.ll, tx, ty, lam, l1);
+    float2 a, b, c, d;
+    ihaar4(r, a, b, c, d);
+    return pick4(bx, by, a, b, c, d);
+  }
+}
+
 template <int LEVELS>
 __global__ __launch_bounds__(64) void k_step(const float2 *__restrict__ z, const float2 *__restrict__ pg,
                                              const float2 *x_old, float2 *x_new, float2 *z_new,
                                              float pg_scale, float lam, float beta_arg,
-                                             const int *__restrict__ k_dev, int N,
+                                             const int *__restrict__ k_dev, int use_k, int N,
                                              double *__restrict__ partials) {
   const int lane = threadIdx.x, tx = lane & 7, ty = lane >> 3;
   const int s = blockIdx.z;
   const int px = blockIdx.x * 16 + 2 * tx, py = blockIdx.y * 16 + 2 * ty;
   const size_t o0 = (size_t)s * N * N + (size_t)py * N + px, o1 = o0 + N;
-  float beta = beta_arg;
-  if (k_dev) {
-    const double k = (double)(*k_dev);
-    beta = (float)(k / (k + 3.0));
-  }
+  // unconditional scalar load: its latency overlaps the vector loads below
+  const int kk = *k_dev;
   const float4 z0 = *reinterpret_cast<const float4 *>(z + o0), z1 = *reinterpret_cast<const float4 *>(z + o1);
   const float4 g0 = *reinterpret_cast<const float4 *>(pg + o0), g1 = *reinterpret_cast<const float4 *>(pg + o1);
   const float4 q0 = *reinterpret_cast<const float4 *>(x_old + o0), q1 = *reinterpret_cast<const float4 *>(x_old + o1);
@@ -453,57 +706,25 @@ __global__ __launch_bounds__(64) void k_step(const float2 *__restrict__ z, const
   const float2 b = make_float2(z0.z - pg_scale * g0.z, z0.w - pg_scale * g0.w);
   const float2 c = make_float2(z1.x - pg_scale * g1.x, z1.y - pg_scale * g1.y);
   const float2 d = make_float2(z1.z - pg_scale * g1.z, z1.w - pg_scale * g1.w);
-  double l1 = 0.0;
-  Quad lev[LEVELS];
+  float l1 = 0.f;
   Quad q = haar4(a, b, c, d);
   q.dx = soft_thr(q.dx, lam, l1);
   q.dy = soft_thr(q.dy, lam, l1);
   q.dd = soft_thr(q.dd, lam, l1);
-  if (LEVELS == 1) q.ll = soft_thr(q.ll, lam, l1);
-  lev[0] = q;
-  float2 ll = q.ll;
-#pragma unroll
-  for (int l = 2; l <= LEVELS; ++l) {
-    const int st = 1 << (l - 2);
-    const int bx = (tx >> (l - 2)) & 1, by = (ty >> (l - 2)) & 1;
-    const float2 ox = shfl_xor2(ll, st), oy = shfl_xor2(ll, 8 * st), od = shfl_xor2(ll, 9 * st);
-    float2 A, B, Cc, D;
-    if (!bx && !by) { A = ll; B = ox; Cc = oy; D = od; }
-    else if (bx && !by) { A = ox; B = ll; Cc = od; D = oy; }
-    else if (!bx && by) { A = oy; B = od; Cc = ll; D = ox; }
-    else { A = od; B = oy; Cc = ox; D = ll; }
-    Quad r = haar4(A, B, Cc, D);
-    double l1g = 0.0;   // counted once per lane group
-    r.dx = soft_thr(r.dx, lam, l1g);
-    r.dy = soft_thr(r.dy, lam, l1g);
-    r.dd = soft_thr(r.dd, lam, l1g);
-    if (l == LEVELS) r.ll = soft_thr(r.ll, lam, l1g);
-    if (!(tx & (2 * st - 1)) && !(ty & (2 * st - 1))) l1 += l1g;
-    lev[l - 1] = r;
-    ll = r.ll;
-  }
-#pragma unroll
-  for (int l = LEVELS; l >= 2; --l) {
-    Quad r = lev[l - 1];
-    r.ll = ll;
-    float2 A, B, Cc, D;
-    ihaar4(r, A, B, Cc, D);
-    const int bx = (tx >> (l - 2)) & 1, by = (ty >> (l - 2)) & 1;
-    ll = (!bx && !by) ? A : (bx && !by) ? B : (!bx && by) ? Cc : D;
-  }
-  Quad r1 = lev[0];
-  r1.ll = ll;
+  if constexpr (LEVELS == 1) q.ll = soft_thr(q.ll, lam, l1);
+  q.ll = haar_levels<2, LEVELS>(q.ll, tx, ty, lam, l1);
   float2 na, nb, nc, nd;
-  ihaar4(r1, na, nb, nc, nd);
+  ihaar4(q, na, nb, nc, nd);
   const float2 oa = make_float2(q0.x, q0.y), ob = make_float2(q0.z, q0.w);
   const float2 oc = make_float2(q1.x, q1.y), od = make_float2(q1.z, q1.w);
-  double dx2 = 0.0, xn2 = 0.0;
+  float dx2 = 0.f, xn2 = 0.f;
   auto acc = [&](float2 n, float2 o) {
-    const double ex = (double)n.x - (double)o.x, ey = (double)n.y - (double)o.y;
+    const float ex = n.x - o.x, ey = n.y - o.y;
     dx2 += ex * ex + ey * ey;
-    xn2 += (double)n.x * n.x + (double)n.y * n.y;
+    xn2 += n.x * n.x + n.y * n.y;
   };
   acc(na, oa); acc(nb, ob); acc(nc, oc); acc(nd, od);
+  const float beta = use_k ? (float)((double)kk / ((double)kk + 3.0)) : beta_arg;
   auto mom = [&](float2 n, float2 o) {
     return make_float2(n.x + beta * (n.x - o.x), n.y + beta * (n.y - o.y));
   };
@@ -512,43 +733,29 @@ __global__ __launch_bounds__(64) void k_step(const float2 *__restrict__ z, const
   *reinterpret_cast<float4 *>(x_new + o1) = make_float4(nc.x, nc.y, nd.x, nd.y);
   *reinterpret_cast<float4 *>(z_new + o0) = make_float4(za.x, za.y, zb.x, zb.y);
   *reinterpret_cast<float4 *>(z_new + o1) = make_float4(zc.x, zc.y, zd.x, zd.y);
-  l1 = wave_sum(l1);
-  dx2 = wave_sum(dx2);
-  xn2 = wave_sum(xn2);
+  // per-lane sums (a few FP32 terms each) widen to FP64 for the wave and grid sums
+  const double l1d = wave_sum((double)l1), dx2d = wave_sum((double)dx2), xn2d = wave_sum((double)xn2);
   if (lane == 0) {
     const size_t blk = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    partials[3 * blk + 0] = l1;
-    partials[3 * blk + 1] = dx2;
-    partials[3 * blk + 2] = xn2;
+    partials[3 * blk + 0] = l1d;
+    partials[3 * blk + 1] = dx2d;
+    partials[3 * blk + 2] = xn2d;
   }
 }
 
 // ---------------------------------------------------------------------------
 // Small helpers
-// Sum `width`-strided FP64 partials in a fixed order into out[0..width).
-// If hist != nullptr, also stores them at hist[(*k_dev) * width + ...] and
-// advances the device iteration counter (the solver's step bookkeeping).
-__global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ partials, int count, int width,
-                                                double *__restrict__ out, double *hist, int *k_dev,
-                                                int hist_cap) {
-  __shared__ double s[256];
-  for (int c = 0; c < width; ++c) {
-    double a = 0.0;
-    for (int i = threadIdx.x; i < count; i += 256) a += partials[(size_t)i * width + c];
-    s[threadIdx.x] = a;
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-      if (threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-      out[c] = s[0];
-      if (hist && k_dev) {
-        const int k = *k_dev;
-        if (k < hist_cap) hist[(size_t)k * width + c] = s[0];
-      }
-    }
-    __syncthreads();
+// Sum `width`-strided FP64 partials (width <= 4) in a fixed order into
+// out[0..width) with one wave: lane-strided sums, then a fixed butterfly.  If
+// k_dev is given, also advances the solver's device iteration counter.
+__global__ __launch_bounds__(64) void k_reduce(const double *__restrict__ partials, int count, int width,
+                                               double *__restrict__ out, int *k_dev) {
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < count; i += 64)
+    for (int c = 0; c < width && c < 4; ++c) a[c] += partials[(size_t)i * width + c];
+  for (int c = 0; c < width && c < 4; ++c) {
+    const double v = wave_sum_d(a[c]);
+    if (threadIdx.x == 0) out[c] = v;
   }
   if (threadIdx.x == 0 && k_dev) *k_dev = *k_dev + 1;
 }

@@ -62,17 +62,31 @@ bool supported_n(int n) {
   return false;
 }
 
-int tw_offset(int n) {
-  int off = 0;
-  for (int v : kSupportedN) {
-    if (v == n) return off;
-    off += v;
-  }
-  return -1;
-}
 
 std::mutex g_tw_mu;
 std::vector<int> g_tw_done;
+
+// exp(-2 pi i r k / (Ns R)) for every stage of plan PL, in its TwLayout order
+template <class PL> void fill_plan_tw(std::vector<float2> &h, int base) {
+  for (int st = 0; st < PL::NST; ++st) {
+    const int ns = PL::ns(st), R = PL::R[st];
+    if (ns <= 1) continue;
+    const int off = base + pf::TwLayout<PL>::off(st);
+    for (int k = 0; k < ns; ++k)
+      for (int r = 1; r < R; ++r) {
+        const double a = -2.0 * M_PI * (double)(r * k) / (double)(ns * R);
+        h[off + k * (R - 1) + r - 1] = make_float2((float)std::cos(a), (float)std::sin(a));
+      }
+  }
+}
+
+template <int N> void fill_n(std::vector<float2> &h) {
+  const int b = pf::TwBase<N>::v;
+  fill_plan_tw<typename pf::Plans<N>::F>(h, b + pf::TwBlock<N>::f);
+  fill_plan_tw<typename pf::Plans<N>::I>(h, b + pf::TwBlock<N>::i);
+  fill_plan_tw<typename pf::Plans1D<N>::F>(h, b + pf::TwBlock<N>::f1);
+  fill_plan_tw<typename pf::Plans1D<N>::I>(h, b + pf::TwBlock<N>::i1);
+}
 
 int ensure_twiddles() {
   int dev = 0;
@@ -80,14 +94,15 @@ int ensure_twiddles() {
   std::lock_guard<std::mutex> lk(g_tw_mu);
   if ((int)g_tw_done.size() <= dev) g_tw_done.resize(dev + 1, 0);
   if (g_tw_done[dev]) return PFISTA_OK;
-  std::vector<float2> h(pf::kTwTotal);
-  for (int n : kSupportedN) {
-    const int off = tw_offset(n);
-    for (int m = 0; m < n; ++m) {
-      const double a = -2.0 * M_PI * (double)m / (double)n;
-      h[off + m] = make_float2((float)std::cos(a), (float)std::sin(a));
-    }
-  }
+  std::vector<float2> h(pf::kTwTotal, make_float2(0.f, 0.f));
+  fill_n<64>(h);
+  fill_n<128>(h);
+  fill_n<160>(h);
+  fill_n<192>(h);
+  fill_n<256>(h);
+  fill_n<320>(h);
+  fill_n<384>(h);
+  fill_n<512>(h);
   PF_HIP(hipMemcpyToSymbol(HIP_SYMBOL(pf::g_tw), h.data(), h.size() * sizeof(float2), 0,
                            hipMemcpyHostToDevice));
   g_tw_done[dev] = 1;
@@ -172,10 +187,11 @@ unsigned blocks_for(size_t n) {
 template <int N> struct Ops {
   using Gm = pf::Geo<N>;
 
-  static void row_fwd(const pfista_desc &d, const float2 *x, const float2 *sens, float2 *t, hipStream_t st) {
+  static void row_fwd(const pfista_desc &d, const float2 *x, const float2 *sens, float2 *t, hipStream_t st,
+                      int *k_inc = nullptr) {
     const int tasks = d.slices * N * d.coils;
     const int grid = (tasks + Gm::G - 1) / Gm::G;
-    pf::k_row_fwd<N><<<grid, Gm::ROW_THREADS, 0, st>>>(x, sens, t, d.coils, tasks);
+    pf::k_row_fwd<N><<<grid, Gm::THREADS, 0, st>>>(x, sens, t, d.coils, tasks, k_inc);
   }
 
   template <int MODE>
@@ -183,9 +199,9 @@ template <int N> struct Ops {
                   float a, float b, double *partials, hipStream_t st) {
     const dim3 grid(N / Gm::COLS, d.slices * d.coils);
     if (d.mask_kind == PFISTA_MASK_1D)
-      pf::k_col<N, MODE, 1><<<grid, Gm::COL_THREADS, 0, st>>>(t, kin, kout, mask, d.coils, a, b, partials);
+      pf::k_col<N, MODE, 1><<<grid, Gm::THREADS, 0, st>>>(t, kin, kout, mask, d.coils, a, b, partials);
     else
-      pf::k_col<N, MODE, 0><<<grid, Gm::COL_THREADS, 0, st>>>(t, kin, kout, mask, d.coils, a, b, partials);
+      pf::k_col<N, MODE, 0><<<grid, Gm::THREADS, 0, st>>>(t, kin, kout, mask, d.coils, a, b, partials);
   }
 
   static void row_inv(const pfista_desc &d, const float2 *t, const float2 *sens, float2 *y, const float2 *w,
@@ -194,19 +210,72 @@ template <int N> struct Ops {
     while (rpw * 2 * d.coils <= Gm::G) rpw *= 2;
     const int rows = d.slices * N;
     const int grid = (rows + rpw - 1) / rpw;
-    pf::k_row_inv<N><<<grid, Gm::ROW_THREADS, 0, st>>>(t, sens, y, w, alpha, beta, d.coils, rows, rpw);
+    pf::k_row_inv<N><<<grid, Gm::THREADS, 0, st>>>(t, sens, y, w, alpha, beta, d.coils, rows, rpw);
+  }
+
+  static void row_inv_fwd(const pfista_desc &d, float2 *t, const float2 *sens, float2 *y, const float2 *w,
+                          float alpha, float beta, hipStream_t st) {
+    int rpw = 1;
+    while (rpw * 2 * d.coils <= Gm::G) rpw *= 2;
+    const int rows = d.slices * N;
+    const int grid = (rows + rpw - 1) / rpw;
+    pf::k_row_inv_fwd<N><<<grid, Gm::THREADS, 0, st>>>(t, sens, y, w, alpha, beta, d.coils, rows, rpw);
+  }
+
+  // A chain of m normal applies in which apply k+1's input is apply k's output:
+  //   y_k = alpha_k A^H A y_{k-1} + beta_k w_k,  y_0 = x.
+  // For a 2-D mask the row passes between applies are fused (2m + 1 kernels).
+  static void chain(const pfista_desc &d, const float2 *sens, const uint8_t *mask, const float2 *x, int m,
+                    const float *alpha, const float *beta, const float2 *const *w, float2 *const *y, float2 *t,
+                    hipStream_t st, int *k_inc) {
+    if (d.mask_kind == PFISTA_MASK_1D) {
+      const float2 *src = x;
+      for (int k = 0; k < m; ++k) {
+        normal(d, sens, mask, src, y[k], alpha[k], w[k], beta[k], t, st, k == 0 ? k_inc : nullptr);
+        src = y[k];
+      }
+      return;
+    }
+    const float inv_n2 = (float)(1.0 / ((double)N * N));
+    row_fwd(d, x, sens, t, st, k_inc);
+    for (int k = 0; k < m; ++k) {
+      col<pf::COL_NORMAL>(d, t, nullptr, nullptr, mask, 1.f, 0.f, nullptr, st);
+      if (k + 1 < m)
+        row_inv_fwd(d, t, sens, y[k], w[k], alpha[k] * inv_n2, beta[k], st);
+      else
+        row_inv(d, t, sens, y[k], w[k], alpha[k] * inv_n2, beta[k], st);
+    }
   }
 
   static void normal(const pfista_desc &d, const float2 *sens, const uint8_t *mask, const float2 *x, float2 *y,
-                     float alpha, const float2 *w, float beta, float2 *t, hipStream_t st) {
+                     float alpha, const float2 *w, float beta, float2 *t, hipStream_t st, int *k_inc = nullptr) {
     if (d.mask_kind == PFISTA_MASK_1D) {
-      const dim3 grid(N / Gm::COLS, d.slices);
-      pf::k_normal_1d<N><<<grid, Gm::COL_THREADS, 0, st>>>(x, sens, mask, y, w, alpha / (float)N, beta, d.coils);
+      using G1 = pf::Geo1D<N>;
+      const dim3 grid(N / G1::COLS, d.slices);
+      pf::k_normal_1d<N><<<grid, G1::THREADS, 0, st>>>(x, sens, mask, y, w, alpha / (float)N, beta, d.coils, k_inc);
       return;
     }
-    row_fwd(d, x, sens, t, st);
+    row_fwd(d, x, sens, t, st, k_inc);
     col<pf::COL_NORMAL>(d, t, nullptr, nullptr, mask, 1.f, 0.f, nullptr, st);
     row_inv(d, t, sens, y, w, (float)((double)alpha / ((double)N * N)), beta, st);
+  }
+
+  // number of FP64 partial sums the residual column pass writes
+  static int resid_blocks(const pfista_desc &d) { return (N / Gm::COLS) * d.slices * d.coils; }
+
+  // number of kernel passes of one normal apply, and pass `k` of it alone
+  static int passes(const pfista_desc &d) { return d.mask_kind == PFISTA_MASK_1D ? 1 : 3; }
+  static void pass(int k, const pfista_desc &d, const float2 *sens, const uint8_t *mask, const float2 *x, float2 *y,
+                   float alpha, const float2 *w, float beta, float2 *t, hipStream_t st) {
+    if (d.mask_kind == PFISTA_MASK_1D) {
+      normal(d, sens, mask, x, y, alpha, w, beta, t, st);
+    } else if (k == 0) {
+      row_fwd(d, x, sens, t, st);
+    } else if (k == 1) {
+      col<pf::COL_NORMAL>(d, t, nullptr, nullptr, mask, 1.f, 0.f, nullptr, st);
+    } else {
+      row_inv(d, t, sens, y, w, (float)((double)alpha / ((double)N * N)), beta, st);
+    }
   }
 
   static void forward(const pfista_desc &d, const float2 *sens, const uint8_t *mask, const float2 *x,
@@ -228,15 +297,16 @@ template <int N> struct Ops {
     col<pf::COL_RESID>(d, t, b, nullptr, mask, (float)(a / N), (float)b_scale, partials, st);
   }
 
+  // k_dev: a valid device int; use_k != 0 takes beta = k / (k + 3) from it
   static void step(const pfista_desc &d, const float2 *z, const float2 *pg, const float2 *xo, float2 *xn,
-                   float2 *zn, float pg_scale, float lam, float beta, const int *k_dev, double *partials,
-                   hipStream_t st) {
+                   float2 *zn, float pg_scale, float lam, float beta, const int *k_dev, int use_k,
+                   double *partials, hipStream_t st) {
     const dim3 grid(N / 16, N / 16, d.slices);
     switch (d.haar_levels) {
-      case 1: pf::k_step<1><<<grid, 64, 0, st>>>(z, pg, xo, xn, zn, pg_scale, lam, beta, k_dev, N, partials); break;
-      case 2: pf::k_step<2><<<grid, 64, 0, st>>>(z, pg, xo, xn, zn, pg_scale, lam, beta, k_dev, N, partials); break;
-      case 3: pf::k_step<3><<<grid, 64, 0, st>>>(z, pg, xo, xn, zn, pg_scale, lam, beta, k_dev, N, partials); break;
-      default: pf::k_step<4><<<grid, 64, 0, st>>>(z, pg, xo, xn, zn, pg_scale, lam, beta, k_dev, N, partials); break;
+      case 1: pf::k_step<1><<<grid, 64, 0, st>>>(z, pg, xo, xn, zn, pg_scale, lam, beta, k_dev, use_k, N, partials); break;
+      case 2: pf::k_step<2><<<grid, 64, 0, st>>>(z, pg, xo, xn, zn, pg_scale, lam, beta, k_dev, use_k, N, partials); break;
+      case 3: pf::k_step<3><<<grid, 64, 0, st>>>(z, pg, xo, xn, zn, pg_scale, lam, beta, k_dev, use_k, N, partials); break;
+      default: pf::k_step<4><<<grid, 64, 0, st>>>(z, pg, xo, xn, zn, pg_scale, lam, beta, k_dev, use_k, N, partials); break;
     }
   }
 };
@@ -259,14 +329,14 @@ const float2 *F2(const pfista_c32 *p) { return reinterpret_cast<const float2 *>(
 float2 *F2(pfista_c32 *p) { return reinterpret_cast<float2 *>(p); }
 
 void normal_op(const pfista_desc &d, const pfista_c32 *sens, const uint8_t *mask, const float2 *x, float2 *y,
-               float alpha, const float2 *w, float beta, void *ws, hipStream_t st) {
+               float alpha, const float2 *w, float beta, void *ws, hipStream_t st, int *k_inc = nullptr) {
   const Layout L = layout(d);
   float2 *t = at<float2>(ws, L.t);
-  PF_DISPATCH(d.n, Ops<NN>::normal(d, F2(sens), mask, x, y, alpha, w, beta, t, st));
+  PF_DISPATCH(d.n, Ops<NN>::normal(d, F2(sens), mask, x, y, alpha, w, beta, t, st, k_inc));
 }
 
 void reduce(const double *partials, int count, int width, double *out, int *k_dev, hipStream_t st) {
-  pf::k_reduce<<<1, 256, 0, st>>>(partials, count, width, out, nullptr, k_dev, 0);
+  pf::k_reduce<<<1, 64, 0, st>>>(partials, count, width, out, k_dev);
 }
 
 void norm2_dev(const float2 *v, size_t n, double *partials, double *out, hipStream_t st) {
@@ -276,22 +346,39 @@ void norm2_dev(const float2 *v, size_t n, double *partials, double *out, hipStre
 }
 
 // Horner recursion of the nested form c0 I + N'(c1 I + N'(... c_d I)):
-// d normal applies ping-ponging between `out` and `tmp`, the last landing in out.
-void poly_op(const pfista_desc &d, const pfista_c32 *sens, const uint8_t *mask, double inv_l,
-             const std::vector<double> &c, const float2 *g, float2 *out, float2 *tmp, void *ws, hipStream_t st) {
+// h = c_d g; h = c_i g + N' h for i = d-1 .. 0.  The first apply folds c_d
+// into its alpha; optionally preceded by the gradient apply g = N' z - A'^H b'
+// (then `pre_x` = z, `pre_w` = A'^H b', output in g), all as one chain.
+void grad_poly_op(const pfista_desc &d, const pfista_c32 *sens, const uint8_t *mask, double inv_l,
+                  const std::vector<double> &c, const float2 *pre_x, const float2 *pre_w, float2 *g,
+                  float2 *out, void *ws, hipStream_t st, int *k_inc) {
   const int deg = (int)c.size() - 1;
   const Layout L = layout(d);
-  if (deg == 0) {
-    pf::k_scale<<<blocks_for(L.n_img), 256, 0, st>>>(g, out, L.n_img, (float)c[0]);
-    return;
+  float2 *t = at<float2>(ws, L.t);
+  float alpha[kMaxDegree + 1], beta[kMaxDegree + 1];
+  const float2 *w[kMaxDegree + 1];
+  float2 *y[kMaxDegree + 1];
+  int m = 0;
+  if (pre_x) {
+    alpha[m] = (float)inv_l; beta[m] = -1.f; w[m] = pre_w; y[m] = g; ++m;
   }
-  const float2 *src = g;
   for (int i = 1; i <= deg; ++i) {
-    float2 *dst = ((deg - i) % 2 == 0) ? out : tmp;
-    const float alpha = (float)(i == 1 ? c[deg] * inv_l : inv_l);
-    normal_op(d, sens, mask, src, dst, alpha, g, (float)c[deg - i], ws, st);
-    src = dst;
+    alpha[m] = (float)(i == 1 ? c[deg] * inv_l : inv_l);
+    beta[m] = (float)c[deg - i];
+    w[m] = g;
+    y[m] = out;
+    ++m;
   }
+  if (m > 0) {
+    const float2 *x0 = pre_x ? pre_x : g;
+    PF_DISPATCH(d.n, Ops<NN>::chain(d, F2(sens), mask, x0, m, alpha, beta, w, y, t, st, k_inc));
+  }
+  if (deg == 0 && !pre_x) pf::k_scale<<<blocks_for(L.n_img), 256, 0, st>>>(g, out, L.n_img, (float)c[0]);
+}
+
+void poly_op(const pfista_desc &d, const pfista_c32 *sens, const uint8_t *mask, double inv_l,
+             const std::vector<double> &c, const float2 *g, float2 *out, void *ws, hipStream_t st) {
+  grad_poly_op(d, sens, mask, inv_l, c, nullptr, nullptr, const_cast<float2 *>(g), out, ws, st, nullptr);
 }
 
 int l2_coefficients(int d, std::vector<double> &c) {
@@ -385,7 +472,7 @@ int pfista_poly_apply(const pfista_plan *p, const pfista_c32 *sens, const uint8_
   const size_t nb = L.n_img * sizeof(float2);
   if (overlaps(g, nb, out, nb)) return fail(PFISTA_EINVAL, "out overlaps g");
   std::vector<double> c(coef, coef + degree + 1);
-  poly_op(p->d, sens, mask, inv_l, c, F2(g), F2(out), at<float2>(ws, L.img[0]), ws, stream);
+  poly_op(p->d, sens, mask, inv_l, c, F2(g), F2(out), ws, stream);
   return launch_status("pfista_poly_apply");
 }
 
@@ -405,8 +492,9 @@ int pfista_step(const pfista_plan *p, const pfista_c32 *z, const pfista_c32 *pg,
   const Layout L = layout(p->d);
   if (L.n_img == 0) return PFISTA_OK;
   double *partials = at<double>(ws, L.partials);
+  DevState *ds = at<DevState>(ws, L.state);
   PF_DISPATCH(p->d.n, Ops<NN>::step(p->d, F2(z), F2(pg), F2(x_old), F2(x_new), F2(z_new), 1.f, lambda, beta_k,
-                                    nullptr, partials, stream));
+                                    &ds->k, 0, partials, stream));
   const int nblk = (p->d.n / 16) * (p->d.n / 16) * p->d.slices;
   reduce(partials, nblk, 3, red, nullptr, stream);
   return launch_status("pfista_step");
@@ -459,7 +547,8 @@ int pfista_data_term(const pfista_plan *p, const pfista_c32 *sens, const uint8_t
   DevState *ds = at<DevState>(ws, L.state);
   PF_DISPATCH(p->d.n, Ops<NN>::resid(p->d, F2(sens), mask, F2(x), F2(b), std::sqrt(inv_l), b_scale, t, partials,
                                      stream));
-  const int cnt = (p->d.n / 16) * p->d.slices * p->d.coils;
+  int cnt = 0;
+  PF_DISPATCH(p->d.n, cnt = Ops<NN>::resid_blocks(p->d));
   reduce(partials, cnt, 1, ds->data, nullptr, stream);
   PF_TRY(launch_status("pfista_data_term"));
   double h = 0.0;
@@ -506,6 +595,53 @@ int pfista_power_iteration(const pfista_plan *p, const pfista_c32 *sens, const u
   return PFISTA_OK;
 }
 
+int pfista_profile_normal(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *mask,
+                          const pfista_c32 *x, pfista_c32 *y, int reps, float *pass_ms, int *npasses, void *ws,
+                          hipStream_t stream) {
+  PF_TRY(check_ops(p, sens, mask, ws));
+  if (!pass_ms || !npasses) return fail(PFISTA_EINVAL, "pass_ms/npasses is NULL");
+  if (reps < 1) return fail(PFISTA_EINVAL, "reps must be >= 1");
+  const pfista_desc &d = p->d;
+  int np = 0;
+  PF_DISPATCH(d.n, np = Ops<NN>::passes(d));
+  *npasses = np;
+  for (int k = 0; k < np; ++k) pass_ms[k] = 0.f;
+  if (d.slices == 0) return PFISTA_OK;
+  PF_TRY(check_ptr(x, "x"));
+  PF_TRY(check_ptr(y, "y"));
+  const Layout L = layout(d);
+  const size_t nb = L.n_img * sizeof(float2);
+  if (overlaps(x, nb, y, nb)) return fail(PFISTA_EINVAL, "y overlaps x");
+  float2 *t = at<float2>(ws, L.t);
+  std::vector<hipEvent_t> ev(np + 1, nullptr);
+  for (auto &e : ev) PF_HIP(hipEventCreate(&e));
+  int rc = PFISTA_OK;
+  std::vector<double> tot(np, 0.0);
+  for (int r = 0; r < reps && rc == PFISTA_OK; ++r) {
+    hipError_t he = hipEventRecord(ev[0], stream);
+    for (int k = 0; k < np && he == hipSuccess; ++k) {
+      PF_DISPATCH(d.n, Ops<NN>::pass(k, d, F2(sens), mask, F2(x), F2(y), 1.f, nullptr, 0.f, t, stream));
+      he = hipEventRecord(ev[k + 1], stream);
+    }
+    if (he == hipSuccess) he = hipEventSynchronize(ev[np]);
+    if (he != hipSuccess) {
+      rc = fail(PFISTA_EHIP, "pfista_profile_normal: %s", hipGetErrorString(he));
+      break;
+    }
+    rc = launch_status("pfista_profile_normal");
+    for (int k = 0; k < np && rc == PFISTA_OK; ++k) {
+      float ms = 0.f;
+      he = hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+      if (he != hipSuccess) rc = fail(PFISTA_EHIP, "event timing: %s", hipGetErrorString(he));
+      tot[k] += ms;
+    }
+  }
+  for (auto &e : ev) (void)hipEventDestroy(e);
+  if (rc != PFISTA_OK) return rc;
+  for (int k = 0; k < np; ++k) pass_ms[k] = (float)(tot[k] / reps);
+  return PFISTA_OK;
+}
+
 int pfista_solve(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *mask, const pfista_c32 *b,
                  const pfista_params *prm, pfista_c32 *x_io, pfista_c32 *z_io, double *history,
                  pfista_report *rep, void *ws, hipStream_t stream) {
@@ -546,7 +682,6 @@ int pfista_solve(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *ma
   float2 *ahb = at<float2>(ws, L.img[0]);
   float2 *g = at<float2>(ws, L.img[1]);
   float2 *pgb = at<float2>(ws, L.img[2]);
-  float2 *tmp = at<float2>(ws, L.img[3]);
   float2 *zb = z_io ? F2(z_io) : at<float2>(ws, L.img[4]);
   float2 *x = F2(x_io);
   double *partials = at<double>(ws, L.partials);
@@ -584,22 +719,20 @@ int pfista_solve(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *ma
     pf::k_fill<<<blocks_for(L.n_img), 256, 0, stream>>>(zb, L.n_img, make_float2(0.f, 0.f));
   }
   const int k0 = prm->k0;
-  PF_HIP(hipMemcpyAsync(&ds->k, &k0, sizeof(int), hipMemcpyHostToDevice, stream));
+  const int k_start = k0 - 1;   // the first gradient apply advances it to k0
+  PF_HIP(hipMemcpyAsync(&ds->k, &k_start, sizeof(int), hipMemcpyHostToDevice, stream));
   PF_TRY(launch_status("pfista_solve(setup)"));
 
   const int deg = (int)c.size() - 1;
   const float lam = (float)prm->lambda;
   const int nstep = (d.n / 16) * (d.n / 16) * d.slices;
   auto body = [&]() {
-    // g = N' z - A'^H b'
-    normal_op(d, sens, mask, zb, g, (float)inv_l, ahb, -1.f, ws, stream);
-    if (deg == 0) {
-      PF_DISPATCH(d.n, Ops<NN>::step(d, zb, g, x, x, zb, (float)c[0], lam, 0.f, &ds->k, partials, stream));
-    } else {
-      poly_op(d, sens, mask, inv_l, c, g, pgb, tmp, ws, stream);
-      PF_DISPATCH(d.n, Ops<NN>::step(d, zb, pgb, x, x, zb, 1.f, lam, 0.f, &ds->k, partials, stream));
-    }
-    reduce(partials, nstep, 3, ds->red, &ds->k, stream);
+    // g = N' z - A'^H b' then pg = p(N') g as one chain of d + 1 applies (its
+    // first kernel advances the iteration counter k); then the fused step
+    grad_poly_op(d, sens, mask, inv_l, c, zb, ahb, g, pgb, ws, stream, &ds->k);
+    const float2 *pg = deg == 0 ? g : pgb;
+    const float pg_scale = deg == 0 ? (float)c[0] : 1.f;
+    PF_DISPATCH(d.n, Ops<NN>::step(d, zb, pg, x, x, zb, pg_scale, lam, 0.f, &ds->k, 1, partials, stream));
   };
 
   hipGraphExec_t gexec = nullptr;
@@ -633,6 +766,8 @@ int pfista_solve(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *ma
     }
     for (; left > 0; --left) body();
     done += chunk;
+    // FP64 sums of the last step of the chunk (its partials are still in place)
+    reduce(partials, nstep, 3, ds->red, nullptr, stream);
     int lrc = launch_status("pfista_solve(loop)");
     if (lrc != PFISTA_OK) {
       if (gexec) (void)hipGraphExecDestroy(gexec);
@@ -642,7 +777,9 @@ int pfista_solve(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *ma
     if (prm->eval_objective) {
       PF_DISPATCH(d.n, Ops<NN>::resid(d, F2(sens), mask, x, F2(b), std::sqrt(inv_l), 1.0 / bnorm,
                                       at<float2>(ws, L.t), partials, stream));
-      reduce(partials, (d.n / 16) * d.slices * d.coils, 1, ds->data, nullptr, stream);
+      int cnt = 0;
+      PF_DISPATCH(d.n, cnt = Ops<NN>::resid_blocks(d));
+      reduce(partials, cnt, 1, ds->data, nullptr, stream);
     }
     hipError_t me = hipMemcpyAsync(h, ds->red, 4 * sizeof(double), hipMemcpyDeviceToHost, stream);
     if (me == hipSuccess) me = hipStreamSynchronize(stream);
