@@ -10,10 +10,13 @@ normal apply, d Horner normal applies and the fused prox/momentum step, all on
 the GPU.  ``value`` = A^H A applies per second over exactly --steps timed
 iterations (inputs resident in HBM, graph-replayed loop).  Also reported:
 
-* roofline of the dominant kernel pass, timed live with HIP events on the
-  launch stream (pfista_profile_normal);
-* time to 1e-4 relative objective error, plain FISTA vs PFISTA d = 1..5 on the
-  same GPU (each method against its own converged objective);
+* roofline of the dominant kernel (the column transform pass, d + 1 launches
+  per iteration), timed live with HIP events on the launch stream;
+* time to tolerance, plain FISTA vs PFISTA d = 1..5 on the same GPU: the
+  relative objective error (1e-4, the headline criterion) and the paper's
+  relative iterate error, each method against its own converged solution;
+* the slab workload (32 slices 384 x 384, 32 coils, phase-encode mask): the
+  HBM-streaming normal operator and a degree-4 PFISTA iteration;
 * the FP64 oracle timed on the host cores on a bounded sample (cpu_baseline).
 
 Prints one JSON line on stdout; progress goes to stderr.
@@ -34,7 +37,7 @@ if ROOT not in sys.path:
 
 WORKLOAD = 2
 PEAK_HBM_GBS = 8000.0
-# FP32 vector FMA issue rate without packed-FP32 instructions:
+# FP32 vector FMA rate without packed-FP32 instructions (which the build disables):
 # 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz
 PEAK_FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
@@ -47,23 +50,50 @@ def fft_flops(n):
     return 5.0 * n * math.log2(n)
 
 
-def pass_model(n, coils, slices, kind):
-    """Algorithmic flops and bytes of each kernel pass of one normal apply
-    (5 N log2 N flops per length-N complex transform, 6 per complex product,
-    8 per complex multiply-add; bytes = what the pass must read and write)."""
+def pass_model(n, coils, slices, kind, degree):
+    """(name, flops, bytes, launches per PFISTA iteration) of each kernel pass:
+    5 N log2 N flops per length-N complex DFT, 6 per complex product, 8 per
+    complex multiply-add; bytes = what the pass must read and write."""
     img, coil = slices * n * n * 8, slices * coils * n * n * 8
     if kind == "1d":
-        fl = slices * coils * n * (2 * fft_flops(n) + 6 * n + 8 * n)
-        return [("phase_encode_1d", fl, 2 * img + coil + slices * n)]
+        fl = slices * coils * n * (2 * fft_flops(n) + 14 * n)
+        return [("phase_encode_apply", fl, 2 * img + coil + slices * n, degree + 1)]
     rows = slices * coils * n
     return [
-        ("row_forward", rows * (fft_flops(n) + 6 * n), img + 2 * coil),
-        ("column_pair", rows * 2 * fft_flops(n), 2 * coil + slices * n * n),
-        ("row_inverse_combine", rows * (fft_flops(n) + 8 * n), 2 * coil + img),
+        ("row_forward", rows * (fft_flops(n) + 6 * n), img + 2 * coil, 1),
+        ("column_pair", rows * 2 * fft_flops(n), 2 * coil + slices * n * n, degree + 1),
+        ("row_inverse_combine", rows * (fft_flops(n) + 8 * n), 2 * coil + 2 * img, 1),
+        ("row_inverse_forward", rows * (2 * fft_flops(n) + 14 * n), 3 * coil + 3 * img, degree),
     ]
 
 
-def setup(torch, pf, dev):
+def load_traffic(kernel_name):
+    """HBM traffic per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_column_pass_256x16.txt")
+    if not os.path.exists(path):
+        return None
+    src = os.path.join(ROOT, "paper_2204_10252_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(src)):
+        with open(os.path.join(src, f), "rb") as fh:
+            h.update(fh.read())
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("sources_sha256") != h.hexdigest() or vals.get("kernel") != kernel_name:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def setup_w2(torch, pf, dev):
     import numpy as np
 
     from synth import make_inputs
@@ -84,7 +114,7 @@ def setup(torch, pf, dev):
 def timed_solve(torch, pf, plan, sens, mask, b, lam, coef, iters, inv_l, stream, graph_iters, k0=0,
                 x=None, z=None):
     dev = sens.device
-    shp = (1, plan.n, plan.n)
+    shp = (plan.slices, plan.n, plan.n)
     x = torch.empty(shp, dtype=torch.complex64, device=dev) if x is None else x
     z = torch.empty(shp, dtype=torch.complex64, device=dev) if z is None else z
     torch.cuda.synchronize()
@@ -96,44 +126,114 @@ def timed_solve(torch, pf, plan, sens, mask, b, lam, coef, iters, inv_l, stream,
     return time.perf_counter() - t0, rep, x, z
 
 
-def time_to_tolerance(torch, pf, plan, sens, mask, b, lam, inv_l, stream, graph_iters, tol=1e-4,
-                      ref_applies=6000, max_hist_applies=3000):
+def first_stay_below(errs, tol):
+    for k in range(len(errs)):
+        if all(e <= tol for e in errs[k:]):
+            return k + 1
+    return None
+
+
+def time_to_tolerance(torch, pf, plan, sens, mask, b, lam, inv_l, stream, graph_iters,
+                      obj_tols=(1e-4, 1e-6), it_tols=(1e-2, 1e-3), ref_applies=6000,
+                      max_hist_applies=2400):
+    """Iterations and GPU time for each method to reach each tolerance."""
     out = {}
     methods = [("fista", [1.0])] + [(f"pfista_d{d}", pf.poly_coefficients(d)) for d in range(1, 6)]
     for name, coef in methods:
         per = len(coef)
         kref = ref_applies // per
-        x = torch.empty((1, plan.n, plan.n), dtype=torch.complex64, device=sens.device)
-        rep = pf.solve(plan, sens, mask, b, x, lam, coef=coef, max_iter=kref, inv_l=inv_l,
+        shp = (1, plan.n, plan.n)
+        xr = torch.empty(shp, dtype=torch.complex64, device=sens.device)
+        rep = pf.solve(plan, sens, mask, b, xr, lam, coef=coef, max_iter=kref, inv_l=inv_l,
                        check_every=kref // 2, history=True, graph_iters=graph_iters, stream=stream)
         f_half, f_inf = rep["history"][-2], rep["history"][-1]
         kmax = max_hist_applies // per
+        x = torch.empty_like(xr)
+        z = torch.empty_like(xr)
         rep = pf.solve(plan, sens, mask, b, x, lam, coef=coef, max_iter=kmax, inv_l=inv_l,
                        check_every=1, history=True, stream=stream)
-        err = [(f - f_inf) / f_inf for f in rep["history"]]
-        kstar = None
-        for k in range(len(err)):
-            if all(e <= tol for e in err[k:]):
-                kstar = k + 1
-                break
+        ferr = [(f - f_inf) / f_inf for f in rep["history"]]
+        # iterate error against the converged solution, one resumed iteration at a time
+        xnorm = float(torch.linalg.vector_norm(xr))
+        ierr = []
+        for k in range(kmax):
+            pf.solve(plan, sens, mask, b, x, lam, coef=coef, max_iter=1, inv_l=inv_l, z=z, k0=k,
+                     stream=stream)
+            ierr.append(float(torch.linalg.vector_norm(x - xr)) / xnorm)
         entry = {"f_inf": f_inf, "f_inf_drift": abs(f_half - f_inf) / f_inf, "ref_iters": kref,
-                 "applies_per_iter": per}
-        if kstar is not None:
-            ts = []
-            for _ in range(5):
-                dt, _, _, _ = timed_solve(torch, pf, plan, sens, mask, b, lam, coef, kstar, inv_l, stream,
-                                          graph_iters)
-                ts.append(dt)
-            ts.sort()
-            entry.update({"iters": kstar, "applies": kstar * per, "ms": 1e3 * ts[len(ts) // 2]})
-        else:
-            entry.update({"iters": None, "applies": None, "ms": None, "note": f"not within {kmax} iterations"})
+                 "applies_per_iter": per, "objective": {}, "iterate": {}}
+        for kind, errs, tols in (("objective", ferr, obj_tols), ("iterate", ierr, it_tols)):
+            for tol in tols:
+                kstar = first_stay_below(errs, tol)
+                res = {"iters": kstar, "applies": None if kstar is None else kstar * per, "ms": None}
+                if kstar is not None:
+                    ts = sorted(timed_solve(torch, pf, plan, sens, mask, b, lam, coef, kstar, inv_l, stream,
+                                            graph_iters)[0] for _ in range(5))
+                    res["ms"] = round(1e3 * ts[2], 4)
+                entry[kind][f"{tol:g}"] = res
         out[name] = entry
-        log(f"time-to-{tol:g} {name}: {entry.get('iters')} iterations, {entry.get('ms')} ms")
-    fista_ms = out["fista"]["ms"]
-    best = min((v["ms"], k) for k, v in out.items() if k != "fista" and v["ms"] is not None)
-    return {"tol": tol, "methods": out, "best_pfista": best[1],
-            "speedup_vs_fista": (fista_ms / best[0]) if fista_ms and best[0] else None}
+        log(f"time-to-tol {name}: objective {entry['objective']}, iterate {entry['iterate']}")
+    summary = {}
+    for kind, tols in (("objective", obj_tols), ("iterate", it_tols)):
+        for tol in tols:
+            key = f"{tol:g}"
+            fms = out["fista"][kind][key]["ms"]
+            cands = [(v[kind][key]["ms"], k) for k, v in out.items()
+                     if k != "fista" and v[kind][key]["ms"] is not None]
+            if fms and cands:
+                best = min(cands)
+                summary[f"{kind}_{key}"] = {"fista_ms": fms, "best_pfista": best[1], "best_ms": best[0],
+                                             "speedup_vs_fista": round(fms / best[0], 3)}
+    return {"criteria": "relative objective error (F - F_inf)/F_inf and relative iterate error "
+                        "||x_k - x_inf||/||x_inf||, each method against its own converged solution",
+            "summary": summary, "methods": out}
+
+
+def slab_benchmark(torch, pf, dev, stream, reps=20, iters=30, graph_iters=10):
+    """Workload 3: 32 slices 384 x 384, 32 coils, phase-encode mask."""
+    import numpy as np
+
+    from synth import WORKLOADS
+    from synth import generators as g
+    w = WORKLOADS[3]
+    n, coils, S = w.n, w.coils, w.slices
+    sens = torch.empty((S, coils, n, n), dtype=torch.complex64, device=dev)
+    mask = torch.empty((S, n), dtype=torch.uint8, device=dev)
+    img = torch.empty((S, n, n), dtype=torch.complex64, device=dev)
+    for s in range(S):
+        rng = np.random.default_rng(1000 * w.wid + s)          # same draw order as synth.make_slice_inputs
+        img[s].copy_(torch.from_numpy(g.phantom(n, rng).astype(np.complex64)))
+        sens[s].copy_(torch.from_numpy(g.coil_sensitivities(n, coils, rng).astype(np.complex64)))
+        mask[s].copy_(torch.from_numpy(g.mask_phase_encode_1d(n, w.centre, w.extra["n_random_lines"], rng)))
+    plan = pf.Plan(n, coils, S, haar_levels=w.levels, mask_kind=pf.MASK_1D, device=dev)
+    y = torch.empty_like(img)
+    for _ in range(3):
+        pf.normal_apply(plan, sens, mask, img, y, 1.0, stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        pf.normal_apply(plan, sens, mask, img, y, 1.0, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / reps * 1e-3
+    (name, flops, nbytes, _), = pass_model(n, coils, S, "1d", w.degree)
+    # a short PFISTA run on data made by the GPU forward model
+    b = torch.empty((S, coils, n, n), dtype=torch.complex64, device=dev)
+    pf.forward(plan, sens, mask, img, b)
+    lam_max = pf.power_iteration(plan, sens, mask, 30)
+    inv_l = 1.0 / (1.01 * lam_max)
+    coef = pf.poly_coefficients(w.degree)
+    with torch.cuda.stream(stream):
+        timed_solve(torch, pf, plan, sens, mask, b, w.lam, coef, 2, inv_l, stream, graph_iters)
+        dt, _, _, _ = timed_solve(torch, pf, plan, sens, mask, b, w.lam, coef, iters, inv_l, stream, graph_iters)
+    return {"workload": "32 slices 384x384, 32 coils, phase-encode mask R=8", "kernel": name,
+            "normal_apply_us": round(t * 1e6, 2), "applies_per_s": round(1.0 / t, 2),
+            "algorithmic_bytes_per_apply": nbytes, "hbm_gbs": round(nbytes / t / 1e9, 1),
+            "hbm_frac": round(nbytes / t / 1e9 / PEAK_HBM_GBS, 4),
+            "alu_tflops": round(flops / t / 1e12, 3),
+            "alu_frac": round(flops / t / 1e12 / PEAK_FP32_NONPACKED_TFLOPS, 4),
+            "pfista_d4_ms_per_iteration": round(1e3 * dt / iters, 4)}
 
 
 def cpu_baseline(inp, degree, seconds):
@@ -153,7 +253,7 @@ def cpu_baseline(inp, degree, seconds):
         x, z, _ = orc.pfista(sens, inp["mask"], bn, inv_l, inp["lam"], coef, inp["levels"], 1, x0=x, z0=z, k0=k)
         k += 1
     dt = time.perf_counter() - t0
-    return {"value": k * (degree + 1) / dt, "unit": "A^H A applies/s", "cores": 1, "kind": "oracle",
+    return {"value": round(k * (degree + 1) / dt, 3), "unit": "A^H A applies/s", "cores": 1, "kind": "oracle",
             "sample": f"{k} PFISTA iterations (degree {degree}, {k * (degree + 1)} applies) of the "
                       f"256x256 16-coil workload in {dt:.1f} s, complex128 NumPy/SciPy, one thread"}
 
@@ -169,6 +269,12 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-tolerance comparison")
+    ap.add_argument("--no-slab", action="store_true", help="skip the 32-slice slab workload")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="only the per-pass kernel timing (for a matching rocprofv3 kernel-trace run)")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="also run one device-to-device copy of this many MiB (a known-size reference "
+                         "for hardware traffic counters), outside the timed region")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the hot path has no multi-GPU mode "
@@ -181,11 +287,30 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     pf.load_library()
+    if args.calib_copy_mb > 0:
+        nel = args.calib_copy_mb * 2**20 // 4
+        a = torch.ones(nel, dtype=torch.float32, device=dev)
+        c = torch.empty_like(a)
+        torch.cuda.synchronize()
+        c.copy_(a)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.calib_copy_mb} MiB read + {args.calib_copy_mb} MiB written")
+        del a, c
     log("building inputs")
-    inp, plan, sens, mask, b, inv_l = setup(torch, pf, dev)
+    inp, plan, sens, mask, b, inv_l = setup_w2(torch, pf, dev)
     lam, d = inp["lam"], args.degree
     coef = pf.poly_coefficients(d)
     stream = torch.cuda.Stream()
+
+    if args.profile_only:
+        with torch.cuda.stream(stream):
+            x = torch.zeros((1, plan.n, plan.n), dtype=torch.complex64, device=dev)
+            pf.solve(plan, sens, mask, b, x, lam, coef=coef, max_iter=args.warmup, inv_l=inv_l, stream=stream)
+            y = torch.empty_like(x)
+            pass_ms = pf.profile_normal(plan, sens, mask, x, y, reps=args.profile_reps, stream=stream)
+        model = pass_model(plan.n, plan.coils, 1, "2d", d)
+        print(json.dumps({m[0]: round(t * 1e3, 3) for m, t in zip(model, pass_ms)}), flush=True)
+        return
 
     with torch.cuda.stream(stream):
         log(f"warmup {args.warmup} iterations")
@@ -198,30 +323,38 @@ def main():
         value = applies / dt
         log(f"{value:.0f} applies/s, {1e3 * dt / args.steps:.4f} ms/iteration")
 
-        # dominant kernel pass, timed live with HIP events on the launch stream
+        # kernel passes, each timed live with HIP events over back-to-back launches
         y = torch.empty_like(x)
         pass_ms = pf.profile_normal(plan, sens, mask, x, y, reps=args.profile_reps, stream=stream)
-        model = pass_model(plan.n, plan.coils, 1, "2d")
-        k = max(range(len(pass_ms)), key=lambda i: pass_ms[i])
-        name, flops, nbytes = model[k]
+        model = pass_model(plan.n, plan.coils, 1, "2d", d)
+        per_iter = [m[3] * t for m, t in zip(model, pass_ms)]
+        k = max(range(len(model)), key=lambda i: per_iter[i])
+        name, flops, nbytes, nl = model[k]
         t_k = pass_ms[k] * 1e-3
         achieved_tf = flops / t_k / 1e12
+        traffic = load_traffic(name)
         roofline = {"bound": "alu", "kernel": name, "achieved": round(achieved_tf, 3),
                     "peak": round(PEAK_FP32_NONPACKED_TFLOPS, 1), "unit": "TFLOP/s",
-                    "frac": round(achieved_tf / PEAK_FP32_NONPACKED_TFLOPS, 4), "traffic": None,
-                    "avg_launch_us": round(pass_ms[k] * 1e3, 3),
+                    "frac": round(achieved_tf / PEAK_FP32_NONPACKED_TFLOPS, 4), "traffic": traffic,
+                    "launches_per_iteration": nl, "avg_launch_us": round(pass_ms[k] * 1e3, 3),
                     "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": nbytes,
                     "hbm_frac": round(nbytes / t_k / 1e9 / PEAK_HBM_GBS, 4),
                     "passes_us": {m[0]: round(t * 1e3, 3) for m, t in zip(model, pass_ms)}}
-        apply_bytes = 8 * plan.n * plan.n * (plan.coils + 2)
-        apply_us = sum(pass_ms) * 1e3
+        apply_us = sum(pass_ms[:3]) * 1e3
         roofline["normal_apply_us"] = round(apply_us, 3)
-        roofline["normal_apply_hbm_frac"] = round(apply_bytes / (apply_us * 1e-6) / 1e9 / PEAK_HBM_GBS, 4)
         log(f"passes (us): {roofline['passes_us']}")
 
         ttt = None
         if not args.no_ttt:
             ttt = time_to_tolerance(torch, pf, plan, sens, mask, b, lam, inv_l, stream, args.graph_iters)
+
+    slab = None
+    if not args.no_slab:
+        log("slab workload")
+        del x, z, y
+        torch.cuda.empty_cache()
+        slab = slab_benchmark(torch, pf, dev, stream, graph_iters=args.graph_iters)
+        log(f"slab: {slab}")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -247,6 +380,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "time_to_tol": ttt,
+        "slab": slab,
     }
     print(json.dumps(out), flush=True)
 

@@ -146,12 +146,14 @@ int pfista_power_iteration(const pfista_plan *p, const pfista_c32 *sens, const u
  * shifted-Legendre kernel, one final rounding.  0 <= degree <= 8. */
 int pfista_poly_coefficients(int degree, double *coef);
 
-/* Per-pass timing of the normal operator (y = A^H A x): runs `reps` applies,
- * recording HIP events on `stream` between the kernel passes, and returns the
- * average duration of each pass in HOST pass_ms (ms) with their count in
- * *npasses (3 for a 2-D mask: row transforms, column transform pair, row
- * inverse + coil combine; 1 for a phase-encode mask).  pass_ms must hold 3
- * floats.  Synchronous.  For profiling only; results equal pfista_normal_apply. */
+/* Per-pass timing of the normal operator (y = A^H A x): each kernel pass is
+ * launched `reps` times back to back between two HIP events on `stream`; HOST
+ * pass_ms[k] receives the average duration (ms) of pass k and *npasses their
+ * count: 4 for a 2-D mask (row transforms; column transform pair with the mask;
+ * inverse rows + coil combine; inverse rows + coil combine fused with the next
+ * apply's forward rows, as in the polynomial chain), 1 for a phase-encode mask.
+ * pass_ms must hold 4 floats.  Synchronous.  For profiling: y ends up holding
+ * the result of the last timed pass, not a defined function of x. */
 int pfista_profile_normal(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *mask,
                           const pfista_c32 *x, pfista_c32 *y, int reps, float *pass_ms, int *npasses,
                           void *ws, hipStream_t stream);

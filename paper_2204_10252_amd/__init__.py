@@ -261,7 +261,7 @@ def power_iteration(plan, sens, mask, iters, v=None, stream=None) -> float:
 def profile_normal(plan, sens, mask, x, y, reps=50, stream=None) -> list:
     """Average duration (ms) of each kernel pass of one normal apply."""
     c = _cplx()
-    ms = (ctypes.c_float * 3)()
+    ms = (ctypes.c_float * 4)()
     npass = ctypes.c_int()
     _check(load_library().pfista_profile_normal(
         plan.handle, _ptr(sens, "sens", c, plan.n_coil), _ptr(mask, "mask", _u8(), plan.mask_numel),

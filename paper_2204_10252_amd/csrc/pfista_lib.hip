@@ -263,8 +263,10 @@ template <int N> struct Ops {
   // number of FP64 partial sums the residual column pass writes
   static int resid_blocks(const pfista_desc &d) { return (N / Gm::COLS) * d.slices * d.coils; }
 
-  // number of kernel passes of one normal apply, and pass `k` of it alone
-  static int passes(const pfista_desc &d) { return d.mask_kind == PFISTA_MASK_1D ? 1 : 3; }
+  // kernel passes timed by pfista_profile_normal: the three passes of one apply
+  // and the fused inverse+forward row pass of the Horner chain (2-D mask), or
+  // the single phase-encode pass; `pass` launches pass k alone
+  static int passes(const pfista_desc &d) { return d.mask_kind == PFISTA_MASK_1D ? 1 : 4; }
   static void pass(int k, const pfista_desc &d, const float2 *sens, const uint8_t *mask, const float2 *x, float2 *y,
                    float alpha, const float2 *w, float beta, float2 *t, hipStream_t st) {
     if (d.mask_kind == PFISTA_MASK_1D) {
@@ -273,8 +275,10 @@ template <int N> struct Ops {
       row_fwd(d, x, sens, t, st);
     } else if (k == 1) {
       col<pf::COL_NORMAL>(d, t, nullptr, nullptr, mask, 1.f, 0.f, nullptr, st);
-    } else {
+    } else if (k == 2) {
       row_inv(d, t, sens, y, w, (float)((double)alpha / ((double)N * N)), beta, st);
+    } else {
+      row_inv_fwd(d, t, sens, y, w, (float)((double)alpha / ((double)N * N)), beta, st);
     }
   }
 
@@ -613,33 +617,30 @@ int pfista_profile_normal(const pfista_plan *p, const pfista_c32 *sens, const ui
   const size_t nb = L.n_img * sizeof(float2);
   if (overlaps(x, nb, y, nb)) return fail(PFISTA_EINVAL, "y overlaps x");
   float2 *t = at<float2>(ws, L.t);
-  std::vector<hipEvent_t> ev(np + 1, nullptr);
-  for (auto &e : ev) PF_HIP(hipEventCreate(&e));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  PF_HIP(hipEventCreate(&e0));
+  PF_HIP(hipEventCreate(&e1));
   int rc = PFISTA_OK;
-  std::vector<double> tot(np, 0.0);
-  for (int r = 0; r < reps && rc == PFISTA_OK; ++r) {
-    hipError_t he = hipEventRecord(ev[0], stream);
-    for (int k = 0; k < np && he == hipSuccess; ++k) {
+  // each pass `reps` times back to back (every pass leaves valid inputs for the
+  // next: the column pass is a projection, the row passes recompute their outputs)
+  for (int k = 0; k < np && rc == PFISTA_OK; ++k) {
+    hipError_t he = hipEventRecord(e0, stream);
+    for (int r = 0; r < reps && he == hipSuccess; ++r)
       PF_DISPATCH(d.n, Ops<NN>::pass(k, d, F2(sens), mask, F2(x), F2(y), 1.f, nullptr, 0.f, t, stream));
-      he = hipEventRecord(ev[k + 1], stream);
-    }
-    if (he == hipSuccess) he = hipEventSynchronize(ev[np]);
+    if (he == hipSuccess) he = hipEventRecord(e1, stream);
+    if (he == hipSuccess) he = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
     if (he != hipSuccess) {
       rc = fail(PFISTA_EHIP, "pfista_profile_normal: %s", hipGetErrorString(he));
       break;
     }
     rc = launch_status("pfista_profile_normal");
-    for (int k = 0; k < np && rc == PFISTA_OK; ++k) {
-      float ms = 0.f;
-      he = hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
-      if (he != hipSuccess) rc = fail(PFISTA_EHIP, "event timing: %s", hipGetErrorString(he));
-      tot[k] += ms;
-    }
+    pass_ms[k] = ms / (float)reps;
   }
-  for (auto &e : ev) (void)hipEventDestroy(e);
-  if (rc != PFISTA_OK) return rc;
-  for (int k = 0; k < np; ++k) pass_ms[k] = (float)(tot[k] / reps);
-  return PFISTA_OK;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
 }
 
 int pfista_solve(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *mask, const pfista_c32 *b,
