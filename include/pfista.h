@@ -158,6 +158,18 @@ int pfista_profile_normal(const pfista_plan *p, const pfista_c32 *sens, const ui
                           const pfista_c32 *x, pfista_c32 *y, int reps, float *pass_ms, int *npasses,
                           void *ws, hipStream_t stream);
 
+/* Weighted L2 design of Section 2.5 with the weight w(z) = z^alpha
+ * (alpha > -1; alpha = 0 is pfista_poly_coefficients): minimise
+ * int_0^1 z^alpha (1 - z q(z))^2 dz.  HOST coef[0..degree], ascending powers;
+ * long-double Gaussian elimination of the moment system.  0 <= degree <= 8. */
+int pfista_poly_coefficients_weighted(int degree, double alpha, double *coef);
+
+/* L-infinity design of Section 2.5 for a known smallest eigenvalue mu in (0, 1)
+ * of the normalised A^H A: p(z) = (1 - r(z)) / z with
+ * r(z) = T_(d+1)((1 + mu - 2z)/(1 - mu)) / T_(d+1)((1 + mu)/(1 - mu)).
+ * HOST coef[0..degree], ascending powers.  0 <= degree <= 8. */
+int pfista_poly_coefficients_chebyshev(int degree, double mu, double *coef);
+
 typedef struct {
   double lambda;       /* l1 weight in normalised units */
   double inv_l;        /* 1/L > 0; 0: estimate L = 1.01 * power iteration */
@@ -173,6 +185,8 @@ typedef struct {
   int k0;              /* resume: iterations already done; x_io, z_io hold x_k0, z_k0 */
   int graph_iters;     /* > 0: replay the loop as a HIP graph of this many
                           iterations (needs a non-default stream); 0: launches */
+  int momentum;        /* 1: FISTA momentum (Algorithms 2 and 4); 0: none, i.e.
+                          PGD / PPGD (Algorithms 1 and 3) */
 } pfista_params;
 
 typedef struct {

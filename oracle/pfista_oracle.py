@@ -32,6 +32,7 @@ __all__ = [
     "kspace_data", "l2_poly_coefficients", "poly_eval", "poly_apply",
     "haar_fwd", "haar_inv", "soft_threshold", "prox_l1_haar", "objective",
     "data_term", "power_iteration", "pfista", "pfista_step", "normalise",
+    "chebyshev_poly_coefficients", "weighted_l2_poly_coefficients", "pgd",
 ]
 
 _SQRT_HALF = np.sqrt(0.5)
@@ -128,16 +129,66 @@ def l2_poly_coefficients(degree: int) -> list:
         raise ValueError("degree must be >= 0")
     a = [[Fraction(1, i + j + 3) for j in range(d + 1)] + [Fraction(1, i + 2)]
          for i in range(d + 1)]
-    for col in range(d + 1):
-        piv = next(r for r in range(col, d + 1) if a[r][col] != 0)
+    return _solve_exact(a)
+
+
+def _solve_exact(a):
+    """Gauss-Jordan elimination over the rationals of an augmented matrix."""
+    n = len(a)
+    for col in range(n):
+        piv = next(r for r in range(col, n) if a[r][col] != 0)
         a[col], a[piv] = a[piv], a[col]
         p = a[col][col]
         a[col] = [v / p for v in a[col]]
-        for r in range(d + 1):
+        for r in range(n):
             if r != col and a[r][col] != 0:
                 f = a[r][col]
                 a[r] = [vr - f * vc for vr, vc in zip(a[r], a[col])]
-    return [a[i][d + 1] for i in range(d + 1)]
+    return [a[i][n] for i in range(n)]
+
+
+def weighted_l2_poly_coefficients(degree: int, alpha) -> list:
+    """Coefficients of the minimiser of ``int_0^1 z^alpha (1 - z q(z))^2 dz``
+    (the weighted cost of Section 2.5 with the weight ``w(z) = z^alpha``,
+    alpha > -1).  With moments ``m_k = int_0^1 z^(alpha + k) dz = 1/(alpha+k+1)``
+    the normal equations are ``sum_j c_j m_(i+j+2) = m_(i+1)``; solved exactly
+    for rational alpha (floats are taken at their exact binary value)."""
+    d = int(degree)
+    al = Fraction(alpha)
+    if al <= -1:
+        raise ValueError("alpha must be > -1")
+    m = [1 / (al + k + 1) for k in range(2 * d + 3)]
+    a = [[m[i + j + 2] for j in range(d + 1)] + [m[i + 1]] for i in range(d + 1)]
+    return _solve_exact(a)
+
+
+def chebyshev_poly_coefficients(degree: int, mu) -> list:
+    """Coefficients of ``p(z) = (1 - r(z)) / z`` with the shifted, scaled
+    Chebyshev residual ``r(z) = T_(d+1)((1 + mu - 2z)/(1 - mu)) /
+    T_(d+1)((1 + mu)/(1 - mu))`` (the L-infinity design of Section 2.5 for a
+    known smallest eigenvalue mu in (0, 1)).  Built exactly from the recurrence
+    ``T_(n+1)(u) = 2u T_n(u) - T_(n-1)(u)`` in powers of z."""
+    d = int(degree)
+    m = Fraction(mu)
+    if not (0 < m < 1):
+        raise ValueError("mu must lie in (0, 1)")
+    u = [(1 + m) / (1 - m), -2 / (1 - m)]          # u(z) = u0 + u1 z
+
+    def mul_u(pz):
+        out = [Fraction(0)] * (len(pz) + 1)
+        for i, c in enumerate(pz):
+            out[i] += u[0] * c
+            out[i + 1] += u[1] * c
+        return out
+
+    t_prev, t_cur = [Fraction(1)], list(u)
+    for _ in range(d):
+        nxt = [2 * c for c in mul_u(t_cur)]
+        for i, c in enumerate(t_prev):
+            nxt[i] -= c
+        t_prev, t_cur = t_cur, nxt
+    r = [c / t_cur[0] for c in t_cur]              # T_(d+1)(u(0)) = t_cur[0]
+    return [-r[j + 1] for j in range(d + 1)]
 
 
 def poly_eval(coef, z):
@@ -238,6 +289,21 @@ def pfista_step(z, pg, x_old, lam, levels, beta):
     x_new = prox_l1_haar(z - pg, lam, levels)
     z_new = x_new + beta * (x_new - x_old)
     return x_new, z_new
+
+
+def pgd(sens, mask, bn, scale, lam, coef, levels, iters, x0=None, history=False):
+    """Proximal gradient descent with the polynomial preconditioner: Algorithm 3
+    (PPGD), or Algorithm 1 (PGD) when coef = [1]:
+    ``y_(k+1) = prox(y_k - p(N')(N' y_k - A'^H b'))`` from ``y_0 = 0``."""
+    ahb = scale ** 0.5 * adjoint(sens, mask, bn)
+    y = np.zeros_like(ahb) if x0 is None else np.array(x0, dtype=np.complex128)
+    hist = []
+    for _ in range(iters):
+        g = normal(sens, mask, y, scale) - ahb
+        y = prox_l1_haar(y - poly_apply(sens, mask, scale, coef, g), lam, levels)
+        if history:
+            hist.append(objective(sens, mask, bn, scale, y, lam, levels))
+    return y, hist
 
 
 def pfista(sens, mask, bn, scale, lam, coef, levels, iters, x0=None, z0=None, k0=0,

@@ -15,7 +15,7 @@ import re
 
 __all__ = [
     "Plan", "PfistaError", "load_library", "library_path", "poly_coefficients",
-    "normal_apply", "poly_apply", "step", "forward", "adjoint", "data_term",
+    "poly_coefficients_weighted", "poly_coefficients_chebyshev", "normal_apply", "poly_apply", "step", "forward", "adjoint", "data_term",
     "power_iteration", "profile_normal", "solve", "MASK_2D", "MASK_1D", "header_functions",
 ]
 
@@ -42,7 +42,7 @@ class _Params(ctypes.Structure):
                 ("coef", ctypes.POINTER(ctypes.c_double)), ("max_iter", ctypes.c_int),
                 ("check_every", ctypes.c_int), ("tol", ctypes.c_double),
                 ("f_stop", ctypes.c_double), ("eval_objective", ctypes.c_int),
-                ("k0", ctypes.c_int), ("graph_iters", ctypes.c_int)]
+                ("k0", ctypes.c_int), ("graph_iters", ctypes.c_int), ("momentum", ctypes.c_int)]
 
 
 class _Report(ctypes.Structure):
@@ -64,6 +64,8 @@ _SIGS = {
     "pfista_data_term": (_I, [_VP, _VP, _VP, _VP, _VP, _D, _D, ctypes.POINTER(_D), _VP, _VP]),
     "pfista_power_iteration": (_I, [_VP, _VP, _VP, _VP, _I, ctypes.POINTER(_D), _VP, _VP]),
     "pfista_poly_coefficients": (_I, [_I, ctypes.POINTER(_D)]),
+    "pfista_poly_coefficients_weighted": (_I, [_I, _D, ctypes.POINTER(_D)]),
+    "pfista_poly_coefficients_chebyshev": (_I, [_I, _D, ctypes.POINTER(_D)]),
     "pfista_solve": (_I, [_VP, _VP, _VP, _VP, ctypes.POINTER(_Params), _VP, _VP,
                           ctypes.POINTER(_D), ctypes.POINTER(_Report), _VP, _VP]),
     "pfista_profile_normal": (_I, [_VP, _VP, _VP, _VP, _VP, _I, ctypes.POINTER(_F),
@@ -191,6 +193,20 @@ def poly_coefficients(degree: int) -> list:
     return list(buf)
 
 
+def poly_coefficients_weighted(degree: int, alpha: float) -> list:
+    """Weighted L2 design with w(z) = z^alpha (Section 2.5)."""
+    buf = (ctypes.c_double * (degree + 1))()
+    _check(load_library().pfista_poly_coefficients_weighted(int(degree), float(alpha), buf))
+    return list(buf)
+
+
+def poly_coefficients_chebyshev(degree: int, mu: float) -> list:
+    """L-infinity design for a known smallest eigenvalue mu (Section 2.5)."""
+    buf = (ctypes.c_double * (degree + 1))()
+    _check(load_library().pfista_poly_coefficients_chebyshev(int(degree), float(mu), buf))
+    return list(buf)
+
+
 def normal_apply(plan, sens, mask, x, y, alpha=1.0, w=None, beta=0.0, stream=None):
     c = _cplx()
     _check(load_library().pfista_normal_apply(
@@ -272,7 +288,7 @@ def profile_normal(plan, sens, mask, x, y, reps=50, stream=None) -> list:
 
 def solve(plan, sens, mask, b, x, lam, degree=3, coef=None, max_iter=50, inv_l=0.0, power_iters=30,
           check_every=None, tol=0.0, f_stop=0.0, eval_objective=False, z=None, k0=0, graph_iters=0,
-          history=False, stream=None, raise_on_diverge=True):
+          history=False, stream=None, raise_on_diverge=True, momentum=True):
     """Algorithm 4 through ``pfista_solve``; returns the report as a dict (with
     ``history`` when asked)."""
     c = _cplx()
@@ -286,7 +302,7 @@ def solve(plan, sens, mask, b, x, lam, degree=3, coef=None, max_iter=50, inv_l=0
     prm = _Params(float(lam), float(inv_l), int(power_iters), int(degree),
                   ctypes.cast(carr, ctypes.POINTER(ctypes.c_double)) if carr is not None else None,
                   int(max_iter), ce, float(tol), float(f_stop), int(bool(eval_objective or history)),
-                  int(k0), int(graph_iters))
+                  int(k0), int(graph_iters), int(bool(momentum)))
     nh = max(1, -(-int(max_iter) // ce))
     hist = (ctypes.c_double * nh)() if history else None
     rep = _Report()

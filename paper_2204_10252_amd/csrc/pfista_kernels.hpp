@@ -54,7 +54,7 @@ template <> struct Plans1D<384> { using F = Plan<384, 32, 12, 4, 4, 2>; using I 
 template <> struct Plans1D<320> { using F = Plan<320, 32, 10, 4, 8>; using I = Plan<320, 32, 8, 4, 10>; };
 template <> struct Plans1D<512> { using F = Plan<512, 32, 16, 4, 8>; using I = Plan<512, 32, 8, 4, 16>; };
 
-template <class F, class I> struct PairGeo {
+template <class F, class I, int WAVES = 4> struct PairGeo {
   static constexpr int N = F::N;
   static constexpr int T = F::T;
   static_assert(I::T == T && I::N == N, "mirrored plans share N and T");
@@ -65,16 +65,25 @@ template <class F, class I> struct PairGeo {
   static_assert(P_IN == I::NB_out * I::R_out && P_OUT == I::NB_in * I::R_in, "layouts must match");
   static_assert(P_OUT <= 32, "mask bits must fit one word");
   static constexpr int LDSN = LdsLen<N>::value;
-  static constexpr int THREADS = 256;
+  static constexpr int THREADS = 64 * WAVES;
   static constexpr int G = THREADS / T;   // transforms per workgroup
   static constexpr int CPW = 64 / T;      // columns per wave in column kernels
-  static constexpr int COLS = 4 * CPW;    // columns per column-kernel workgroup
+  static constexpr int COLS = WAVES * CPW;  // columns per column-kernel workgroup
 };
 template <int N> struct Geo : PairGeo<typename Plans<N>::F, typename Plans<N>::I> {
   using F = typename Plans<N>::F;
   using I = typename Plans<N>::I;
 };
-template <int N> struct Geo1D : PairGeo<typename Plans1D<N>::F, typename Plans1D<N>::I> {
+// the phase-encode kernel's blocks span 16 columns (128 B of every row of a
+// coil map) so that no cache line of the streamed coil maps is split between
+// blocks
+#ifndef PF_1D_BLOCK_WAVES
+#define PF_1D_BLOCK_WAVES 0
+#endif
+template <int N> struct Waves1D {
+  static constexpr int v = PF_1D_BLOCK_WAVES > 0 ? PF_1D_BLOCK_WAVES : 16 / (64 / Plans1D<N>::F::T);
+};
+template <int N> struct Geo1D : PairGeo<typename Plans1D<N>::F, typename Plans1D<N>::I, Waves1D<N>::v> {
   using F = typename Plans1D<N>::F;
   using I = typename Plans1D<N>::I;
 };
@@ -499,16 +508,19 @@ __global__ __launch_bounds__(256, 2) void k_row_inv_fwd(float2 *__restrict__ t, 
 // One-pass normal operator for a phase-encode mask (sampled rows ky, all kx):
 // F^H M F = (F_y^H M_y F_y) (x) I, so each column only needs a y transform pair.
 // Block = COLS columns of one slice, wave-private transform groups; all coils
-// are accumulated in registers, the next coil map is prefetched while the
-// current one is transformed.
+// are accumulated in registers; the next coil map is loaded after the
+// current one has been transformed and combined.
 #ifndef PF_1D_WAVES
 #define PF_1D_WAVES 2
 #endif
-#ifndef PF_1D_PREFETCH
-#define PF_1D_PREFETCH 0
+// PF_1D_HOIST: let the compiler keep the per-lane index math of the transforms
+// in registers across the coil loop (a few spilled registers cost less than
+// recomputing it for every coil)
+#ifndef PF_1D_HOIST
+#define PF_1D_HOIST 1
 #endif
 template <int N>
-__global__ __launch_bounds__(256, PF_1D_WAVES) void k_normal_1d(const float2 *__restrict__ x,
+__global__ __launch_bounds__(Geo1D<N>::THREADS, PF_1D_WAVES) void k_normal_1d(const float2 *__restrict__ x,
                                                    const float2 *__restrict__ sens,
                                                    const uint8_t *__restrict__ mask,
                                                    float2 *__restrict__ y, const float2 *w, float alpha,
@@ -551,22 +563,17 @@ __global__ __launch_bounds__(256, PF_1D_WAVES) void k_normal_1d(const float2 *__
   load_tw(s_twI, TwBase<N>::v + TwBlock<N>::i1, TwLayout<I>::size());
   __syncthreads();
   for (int c = 0; c < C; ++c) {
-    float2 v[Gm::P], sn[PI];
+    float2 v[Gm::P];
 #pragma unroll
     for (int i = 0; i < PI; ++i) v[i] = cmul(sc[i], xv[i]);
+#if PF_1D_HOIST
+    const int jl = j0;
+    float2 *bl = s_buf + wv * Gm::CPW * Gm::LDSN + ci;
+#else
     const int jl = opaque(j0);
     float2 *bl = s_buf + wv * Gm::CPW * Gm::LDSN + opaque(ci);
-#if PF_1D_PREFETCH
-    const float2 *snp = ss + (size_t)(c + 1 < C ? c + 1 : c) * N * N;
-    {
-      const int kxl = opaque(kx);
-#pragma unroll
-      for (int i = 0; i < PI; ++i) {
-        const int o = (jl + (i / F::R_in) * T + (i % F::R_in) * F::B_in) * N + kxl;
-        sn[i] = okp(i) ? snp[o] : make_float2(0.f, 0.f);
-      }
-    }
 #endif
+
     fft_run<F, -1, Gm::CPW>(v, bl, jl, s_twF);
 #pragma unroll
     for (int i = 0; i < Gm::P_OUT; ++i)
@@ -574,20 +581,15 @@ __global__ __launch_bounds__(256, PF_1D_WAVES) void k_normal_1d(const float2 *__
     fft_run<I, +1, Gm::CPW>(v, bl, jl, s_twI);
 #pragma unroll
     for (int i = 0; i < PI; ++i) acc[i] = cadd(acc[i], cmulc(v[i], sc[i]));
-#if PF_1D_PREFETCH
-#pragma unroll
-    for (int i = 0; i < PI; ++i) sc[i] = sn[i];
-#else
     if (c + 1 < C) {
       const float2 *snp = ss + (size_t)(c + 1) * N * N;
-      const int kxl = opaque(kx);
+      const int kxl = PF_1D_HOIST ? kx : opaque(kx);
 #pragma unroll
       for (int i = 0; i < PI; ++i) {
         const int o = (jl + (i / F::R_in) * T + (i % F::R_in) * F::B_in) * N + kxl;
         sc[i] = okp(i) ? snp[o] : make_float2(0.f, 0.f);
       }
     }
-#endif
   }
   float2 *ys = y + (size_t)s * N * N;
   const float2 *ws = w ? w + (size_t)s * N * N : nullptr;

@@ -403,6 +403,60 @@ int l2_coefficients(int d, std::vector<double> &c) {
   return PFISTA_OK;
 }
 
+// Weighted L2 design (w(z) = z^alpha): normal equations sum_j c_j m_(i+j+2) =
+// m_(i+1), m_k = 1/(alpha + k + 1), by Gaussian elimination with partial
+// pivoting in long double.
+int weighted_coefficients(int d, double alpha, std::vector<double> &c) {
+  if (d < 0 || d > kMaxDegree) return fail(PFISTA_UNSUPPORTED, "degree %d outside 0..%d", d, kMaxDegree);
+  if (!(alpha > -1.0) || !std::isfinite(alpha)) return fail(PFISTA_EINVAL, "alpha must be finite and > -1");
+  const int n = d + 1;
+  std::vector<long double> a((size_t)n * (n + 1));
+  auto m = [&](int k) { return 1.0L / ((long double)alpha + (long double)k + 1.0L); };
+  for (int i = 0; i < n; ++i) {
+    for (int j = 0; j < n; ++j) a[(size_t)i * (n + 1) + j] = m(i + j + 2);
+    a[(size_t)i * (n + 1) + n] = m(i + 1);
+  }
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < n; ++r)
+      if (std::fabs(a[(size_t)r * (n + 1) + col]) > std::fabs(a[(size_t)piv * (n + 1) + col])) piv = r;
+    if (piv != col)
+      for (int k = 0; k <= n; ++k) std::swap(a[(size_t)col * (n + 1) + k], a[(size_t)piv * (n + 1) + k]);
+    const long double pv = a[(size_t)col * (n + 1) + col];
+    for (int r = 0; r < n; ++r) {
+      if (r == col) continue;
+      const long double f = a[(size_t)r * (n + 1) + col] / pv;
+      for (int k = col; k <= n; ++k) a[(size_t)r * (n + 1) + k] -= f * a[(size_t)col * (n + 1) + k];
+    }
+  }
+  c.resize(n);
+  for (int i = 0; i < n; ++i) c[i] = (double)(a[(size_t)i * (n + 1) + n] / a[(size_t)i * (n + 1) + i]);
+  return PFISTA_OK;
+}
+
+// L-infinity (Chebyshev) design for a known smallest eigenvalue mu in (0, 1):
+// r(z) = T_(d+1)(u0 + u1 z) / T_(d+1)(u0), u0 = (1+mu)/(1-mu), u1 = -2/(1-mu),
+// expanded in powers of z by T_(n+1) = 2u T_n - T_(n-1) (long double); p = (1 - r)/z.
+int chebyshev_coefficients(int d, double mu, std::vector<double> &c) {
+  if (d < 0 || d > kMaxDegree) return fail(PFISTA_UNSUPPORTED, "degree %d outside 0..%d", d, kMaxDegree);
+  if (!(mu > 0.0 && mu < 1.0)) return fail(PFISTA_EINVAL, "mu must lie in (0, 1)");
+  const long double u0 = (1.0L + mu) / (1.0L - mu), u1 = -2.0L / (1.0L - mu);
+  std::vector<long double> tp{1.0L}, tc{u0, u1};
+  for (int it = 0; it < d; ++it) {
+    std::vector<long double> nx(tc.size() + 1, 0.0L);
+    for (size_t i = 0; i < tc.size(); ++i) {
+      nx[i] += 2.0L * u0 * tc[i];
+      nx[i + 1] += 2.0L * u1 * tc[i];
+    }
+    for (size_t i = 0; i < tp.size(); ++i) nx[i] -= tp[i];
+    tp = tc;
+    tc = nx;
+  }
+  c.resize(d + 1);
+  for (int j = 0; j <= d; ++j) c[j] = (double)(-tc[j + 1] / tc[0]);
+  return PFISTA_OK;
+}
+
 }  // namespace
 
 // ============================================================================ C-ABI
@@ -441,6 +495,22 @@ int pfista_poly_coefficients(int degree, double *coef) {
   if (!coef) return fail(PFISTA_EINVAL, "coef is NULL");
   std::vector<double> c;
   PF_TRY(l2_coefficients(degree, c));
+  std::copy(c.begin(), c.end(), coef);
+  return PFISTA_OK;
+}
+
+int pfista_poly_coefficients_weighted(int degree, double alpha, double *coef) {
+  if (!coef) return fail(PFISTA_EINVAL, "coef is NULL");
+  std::vector<double> c;
+  PF_TRY(weighted_coefficients(degree, alpha, c));
+  std::copy(c.begin(), c.end(), coef);
+  return PFISTA_OK;
+}
+
+int pfista_poly_coefficients_chebyshev(int degree, double mu, double *coef) {
+  if (!coef) return fail(PFISTA_EINVAL, "coef is NULL");
+  std::vector<double> c;
+  PF_TRY(chebyshev_coefficients(degree, mu, c));
   std::copy(c.begin(), c.end(), coef);
   return PFISTA_OK;
 }
@@ -733,7 +803,9 @@ int pfista_solve(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *ma
     grad_poly_op(d, sens, mask, inv_l, c, zb, ahb, g, pgb, ws, stream, &ds->k);
     const float2 *pg = deg == 0 ? g : pgb;
     const float pg_scale = deg == 0 ? (float)c[0] : 1.f;
-    PF_DISPATCH(d.n, Ops<NN>::step(d, zb, pg, x, x, zb, pg_scale, lam, 0.f, &ds->k, 1, partials, stream));
+    // momentum off (Algorithms 1 and 3): beta = 0, so z_(k+1) = x_(k+1)
+    const int use_k = prm->momentum ? 1 : 0;
+    PF_DISPATCH(d.n, Ops<NN>::step(d, zb, pg, x, x, zb, pg_scale, lam, 0.f, &ds->k, use_k, partials, stream));
   };
 
   hipGraphExec_t gexec = nullptr;

@@ -60,3 +60,24 @@ def test_null_plan_is_rejected(lib):
     rc = lib.pfista_normal_apply(None, None, None, None, None, 1.0, None, 0.0, None, None)
     assert rc == -1
     assert b"plan" in lib.pfista_last_error()
+
+
+@pytest.mark.parametrize("d", range(0, 7))
+def test_host_weighted_and_chebyshev_coefficients_match_oracle(lib, d):
+    import paper_2204_10252_amd as pf
+    for alpha in (0.0, 0.7, 2.0):
+        want = [float(c) for c in orc.weighted_l2_poly_coefficients(d, alpha)]
+        assert pf.poly_coefficients_weighted(d, alpha) == pytest.approx(want, rel=1e-9, abs=0)
+    for mu in (0.01, 0.1, 0.5):
+        want = [float(c) for c in orc.chebyshev_poly_coefficients(d, mu)]
+        assert pf.poly_coefficients_chebyshev(d, mu) == pytest.approx(want, rel=1e-12, abs=0)
+
+
+def test_host_coefficient_argument_errors(lib):
+    import paper_2204_10252_amd as pf
+    for bad in ((2, -1.0), (2, float("nan"))):
+        with pytest.raises(pf.PfistaError):
+            pf.poly_coefficients_weighted(*bad)
+    for bad in ((2, 0.0), (2, 1.0), (9, 0.5)):
+        with pytest.raises(pf.PfistaError):
+            pf.poly_coefficients_chebyshev(*bad)

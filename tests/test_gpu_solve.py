@@ -135,3 +135,21 @@ def test_lambda_zero_matches_oracle(c1):
     xo, _, _ = orc.pfista(s128, inp["mask"], bn, inv_l, 0.0, orc.l2_poly_coefficients(2),
                           inp["levels"], 40)
     assert rel(x.cpu().numpy(), xo) <= 1e-4
+
+
+@pytest.mark.parametrize("design", ["plain", "l2", "chebyshev", "weighted"])
+def test_pgd_ppgd_and_polynomial_designs(c1, design):
+    # Algorithms 1 and 3 (no momentum) and the Section 2.5 design variants
+    import torch
+    import paper_2204_10252_amd as pf
+    inp, sens, s128, b, bn, inv_l = c1
+    plan = gpu_plan(inp)
+    coef = {"plain": [1.0],
+            "l2": [float(c) for c in orc.l2_poly_coefficients(3)],
+            "chebyshev": [float(c) for c in orc.chebyshev_poly_coefficients(3, 0.05)],
+            "weighted": [float(c) for c in orc.weighted_l2_poly_coefficients(3, 1.0)]}[design]
+    x = torch.empty((1, inp["n"], inp["n"]), dtype=torch.complex64, device="cuda")
+    pf.solve(plan, to_dev(sens), to_dev(inp["mask"]), to_dev(b), x, inp["lam"], coef=coef,
+             max_iter=30, inv_l=inv_l, momentum=False)
+    yo, _ = orc.pgd(s128, inp["mask"], bn, inv_l, inp["lam"], coef, inp["levels"], 30)
+    assert rel(x.cpu().numpy(), yo) <= 1e-4
