@@ -215,6 +215,103 @@ int pfista_solve(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *ma
                  pfista_c32 *z_io, double *history, pfista_report *rep, void *ws,
                  hipStream_t stream);
 
+/* ------------------------------------------------------------------ batches
+ * A batch is a list of independent slices of uneven shape (image side, coil
+ * count, Haar levels), each its own problem of the form above with its own
+ * normalisation (inv_l_s, ||b_s||, Section 3) and its own lambda_s, all run
+ * for the same iterations with one polynomial.  (The Cartesian experiment of
+ * Section 3.2 reconstructs 2-D slices of a many-slice volume; every slice is an
+ * independent instance of the problem.)  2-D masks only.  Slices with the same
+ * image side and levels
+ * form a group; each kernel launch covers a whole group, whatever its slices'
+ * coil counts.  Every group gets its own launch shape from a tuner that times
+ * the candidate radix schedules and coil-combine shapes on the device. */
+typedef struct {
+  int n;           /* image side (as pfista_desc.n) */
+  int coils;       /* >= 1 */
+  int haar_levels; /* 1..4 */
+} pfista_slice_desc;
+
+typedef struct pfista_batch pfista_batch;
+
+/* Launch-shape candidates a group can be forced to (params.tune = k + 1):
+ * candidate k uses radix schedule k % 2 (0: default, 1: twice the lanes per
+ * transform), fuses the Horner row passes unless (k / 2) % 2, and multiplies
+ * the rows per coil-combine block by 2^(k / 4). */
+#define PFISTA_TUNE_CANDIDATES 12
+
+/* Validate and group `count` slices (HOST array); count >= 0, at most 65535
+ * coil images per group.  Returns EINVAL / UNSUPPORTED on a bad slice. */
+int pfista_batch_create(pfista_batch **out, const pfista_slice_desc *slices, int count);
+void pfista_batch_destroy(pfista_batch *b);
+/* Device workspace for pfista_batch_solve: about three times the coil-map
+ * bytes of all slices (normalised copies of maps and data, transform buffer)
+ * plus five images per slice. */
+size_t pfista_batch_workspace_bytes(const pfista_batch *b);
+/* Number of groups (entries of the group report). */
+int pfista_batch_groups(const pfista_batch *b);
+
+typedef struct {
+  int degree;          /* as pfista_params */
+  const double *coef;  /* HOST, degree+1 coefficients; NULL: L2-optimal fit */
+  int max_iter;        /* iterations (all slices run the same count) */
+  int check_every;     /* 1..4096 */
+  double tol;          /* stop when every slice's relative change <= tol at a check; 0 off */
+  int eval_objective;  /* per-slice F(x_k) at each check */
+  int power_iters;     /* power-iteration steps for slices whose inv_l is 0 */
+  int graph_iters;     /* > 0: replay the loop as one HIP graph of this many
+                          iterations over all groups (non-default stream) */
+  int momentum;        /* 1: FISTA momentum; 0: PGD / PPGD */
+  int streams;         /* 1: groups one after another on `stream`; k > 1: groups
+                          spread over k concurrent branches (forked from and
+                          joined back into `stream`) */
+  int tune;            /* -1: tune every group (cached per device architecture,
+                          image side, slice and coil counts, degree; the file
+                          named by PFISTA_TUNE_CACHE, if set, persists the
+                          choices); 0: default shape; k >= 1: candidate k - 1 */
+} pfista_batch_params;
+
+typedef struct {
+  double objective;  /* F_s(x) at the last check (NaN without eval_objective) */
+  double rel_change; /* ||x_k - x_k-1|| / ||x_k|| at the last check */
+  double l1;         /* ||Psi x_k||_1 */
+  double inv_l;      /* 1/L_s used */
+  double bnorm;      /* ||b_s|| */
+} pfista_slice_report;
+
+typedef struct {
+  int n;             /* image side */
+  int haar_levels;
+  int slices;        /* slices in the group */
+  int coil_images;   /* sum of their coil counts */
+  int candidate;     /* launch shape used (see PFISTA_TUNE_CANDIDATES) */
+  double chain_us;   /* tuner's time of one gradient + polynomial chain (0 if not timed) */
+} pfista_group_report;
+
+typedef struct {
+  int iters;
+  int status;
+  long long normal_applies; /* per slice */
+} pfista_batch_report;
+
+/* Algorithm 4 on every slice of the batch.  sens, mask, kspace, x_out: HOST
+ * arrays of `count` device pointers, slice s's coil maps [C_s][n_s][n_s],
+ * 2-D mask uint8 [n_s][n_s], k-space data [C_s][n_s][n_s] and output image
+ * [n_s][n_s] (x_k in normalised units; x_out may not alias the inputs).
+ * lambda: HOST [count].  inv_l: HOST [count] (0 entries are estimated by
+ * power iteration) or NULL (all estimated).  Setup folds sqrt(inv_l_s) into a
+ * copy of the coil maps and 1/||b_s|| into a copy of the data, so the loop is
+ * the single-slice loop with per-slice thresholds.  slice_rep (HOST [count]),
+ * group_rep (HOST [pfista_batch_groups]) and rep may be NULL.  Synchronises
+ * at setup, at checks and on return.  DIVERGED if any slice's values turn
+ * non-finite or its objective exceeds 5. */
+int pfista_batch_solve(const pfista_batch *b, const pfista_c32 *const *sens,
+                       const uint8_t *const *mask, const pfista_c32 *const *kspace,
+                       const double *lambda, const double *inv_l,
+                       const pfista_batch_params *prm, pfista_c32 *const *x_out,
+                       pfista_slice_report *slice_rep, pfista_group_report *group_rep,
+                       pfista_batch_report *rep, void *ws, hipStream_t stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *pfista_last_error(void);
 

@@ -17,6 +17,7 @@ __all__ = [
     "Plan", "PfistaError", "load_library", "library_path", "poly_coefficients",
     "poly_coefficients_weighted", "poly_coefficients_chebyshev", "normal_apply", "poly_apply", "step", "forward", "adjoint", "data_term",
     "power_iteration", "profile_normal", "solve", "MASK_2D", "MASK_1D", "header_functions",
+    "Batch", "batch_solve", "TUNE_CANDIDATES",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -51,6 +52,34 @@ class _Report(ctypes.Structure):
                 ("bnorm", ctypes.c_double), ("normal_applies", ctypes.c_longlong)]
 
 
+class _SliceDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("coils", ctypes.c_int), ("haar_levels", ctypes.c_int)]
+
+
+class _BatchParams(ctypes.Structure):
+    _fields_ = [("degree", ctypes.c_int), ("coef", ctypes.POINTER(ctypes.c_double)),
+                ("max_iter", ctypes.c_int), ("check_every", ctypes.c_int), ("tol", ctypes.c_double),
+                ("eval_objective", ctypes.c_int), ("power_iters", ctypes.c_int),
+                ("graph_iters", ctypes.c_int), ("momentum", ctypes.c_int), ("streams", ctypes.c_int),
+                ("tune", ctypes.c_int)]
+
+
+class _SliceReport(ctypes.Structure):
+    _fields_ = [("objective", ctypes.c_double), ("rel_change", ctypes.c_double), ("l1", ctypes.c_double),
+                ("inv_l", ctypes.c_double), ("bnorm", ctypes.c_double)]
+
+
+class _GroupReport(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("haar_levels", ctypes.c_int), ("slices", ctypes.c_int),
+                ("coil_images", ctypes.c_int), ("candidate", ctypes.c_int), ("chain_us", ctypes.c_double)]
+
+
+class _BatchReport(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("status", ctypes.c_int), ("normal_applies", ctypes.c_longlong)]
+
+
+TUNE_CANDIDATES = 12
+
 _VP, _I, _F, _D = ctypes.c_void_p, ctypes.c_int, ctypes.c_float, ctypes.c_double
 _SIGS = {
     "pfista_plan_create": (_I, [ctypes.POINTER(_VP), ctypes.POINTER(_Desc)]),
@@ -70,6 +99,14 @@ _SIGS = {
                           ctypes.POINTER(_D), ctypes.POINTER(_Report), _VP, _VP]),
     "pfista_profile_normal": (_I, [_VP, _VP, _VP, _VP, _VP, _I, ctypes.POINTER(_F),
                                    ctypes.POINTER(_I), _VP, _VP]),
+    "pfista_batch_create": (_I, [ctypes.POINTER(_VP), ctypes.POINTER(_SliceDesc), _I]),
+    "pfista_batch_destroy": (None, [_VP]),
+    "pfista_batch_workspace_bytes": (ctypes.c_size_t, [_VP]),
+    "pfista_batch_groups": (_I, [_VP]),
+    "pfista_batch_solve": (_I, [_VP, ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.POINTER(_VP),
+                                ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_BatchParams),
+                                ctypes.POINTER(_VP), ctypes.POINTER(_SliceReport),
+                                ctypes.POINTER(_GroupReport), ctypes.POINTER(_BatchReport), _VP, _VP]),
     "pfista_last_error": (ctypes.c_char_p, []),
 }
 
@@ -318,5 +355,93 @@ def solve(plan, sens, mask, b, x, lam, degree=3, coef=None, max_iter=50, inv_l=0
         out["history"] = list(hist)[:nchk]
     if rc != OK and not (rc == DIVERGED and not raise_on_diverge):
         _check(rc)
+    out["rc"] = rc
+    return out
+
+
+# ------------------------------------------------------------------ batches
+
+class Batch:
+    """Owns a ``pfista_batch`` (slices of uneven shape) and its device workspace.
+    ``slices``: sequence of ``(n, coils)`` or ``(n, coils, haar_levels)``."""
+
+    def __init__(self, slices, haar_levels=4, device=None):
+        import torch
+        lib = load_library()
+        sl = [tuple(int(v) for v in t) for t in slices]
+        self.slices = [(t[0], t[1], t[2] if len(t) > 2 else int(haar_levels)) for t in sl]
+        arr = (_SliceDesc * max(1, len(self.slices)))(*[_SliceDesc(*t) for t in self.slices])
+        h = ctypes.c_void_p()
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        with torch.cuda.device(self.device):
+            _check(lib.pfista_batch_create(ctypes.byref(h), arr, len(self.slices)))
+        self._h = h
+        self.groups = int(lib.pfista_batch_groups(h))
+        nbytes = int(lib.pfista_batch_workspace_bytes(h))
+        self.ws = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=self.device)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __len__(self):
+        return len(self.slices)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.pfista_batch_destroy(h)
+            self._h = None
+
+
+def _ptr_array(tensors, name, dtype, numels):
+    arr = (ctypes.c_void_p * max(1, len(tensors)))()
+    for i, (t, nel) in enumerate(zip(tensors, numels)):
+        arr[i] = _ptr(t, f"{name}[{i}]", dtype, nel).value
+    return arr
+
+
+def batch_solve(batch, sens, mask, b, x, lam, degree=3, coef=None, max_iter=50, inv_l=None,
+                power_iters=30, check_every=None, tol=0.0, eval_objective=False, graph_iters=0,
+                momentum=True, streams=1, tune=0, stream=None, raise_on_diverge=True):
+    """Algorithm 4 on every slice of ``batch`` through ``pfista_batch_solve``.
+    ``sens``, ``mask``, ``b``, ``x``: lists of per-slice device tensors; ``lam``
+    and ``inv_l`` (None: estimate all): per-slice floats.  Returns a dict with
+    the batch report, ``slices`` (per-slice reports) and ``groups``."""
+    c = _cplx()
+    lib = load_library()
+    ns = len(batch)
+    for name, v in (("sens", sens), ("mask", mask), ("b", b), ("x", x), ("lam", lam)):
+        if len(v) != ns:
+            raise ValueError(f"{name} has {len(v)} entries for {ns} slices")
+    if inv_l is not None and len(inv_l) != ns:
+        raise ValueError("inv_l needs one entry per slice")
+    coil_n = [cc * n * n for n, cc, _ in batch.slices]
+    img_n = [n * n for n, _, _ in batch.slices]
+    ps = _ptr_array(sens, "sens", c, coil_n)
+    pm = _ptr_array(mask, "mask", _u8(), img_n)
+    pb = _ptr_array(b, "b", c, coil_n)
+    px = _ptr_array(x, "x", c, img_n)
+    lam_a = (ctypes.c_double * max(1, ns))(*[float(v) for v in lam])
+    il_a = (ctypes.c_double * max(1, ns))(*[float(v) for v in inv_l]) if inv_l is not None else None
+    ce = max_iter if check_every is None else check_every
+    ce = max(1, min(int(ce), 4096))
+    carr = None
+    if coef is not None:
+        carr = (ctypes.c_double * len(coef))(*[float(v) for v in coef])
+        degree = len(coef) - 1
+    prm = _BatchParams(int(degree), ctypes.cast(carr, ctypes.POINTER(ctypes.c_double)) if carr is not None else None,
+                       int(max_iter), ce, float(tol), int(bool(eval_objective)), int(power_iters),
+                       int(graph_iters), int(bool(momentum)), int(streams), int(tune))
+    srep = (_SliceReport * max(1, ns))()
+    grep = (_GroupReport * max(1, batch.groups))()
+    rep = _BatchReport()
+    rc = lib.pfista_batch_solve(batch.handle, ps, pm, pb, lam_a, il_a, ctypes.byref(prm), px, srep, grep,
+                                ctypes.byref(rep), _ptr(batch.ws, "ws"), _stream(stream))
+    if rc != OK and not (rc == DIVERGED and not raise_on_diverge):
+        _check(rc)
+    out = {k: getattr(rep, k) for k, _ in _BatchReport._fields_}
+    out["slices"] = [{k: getattr(srep[i], k) for k, _ in _SliceReport._fields_} for i in range(ns)]
+    out["groups"] = [{k: getattr(grep[i], k) for k, _ in _GroupReport._fields_} for i in range(batch.groups)]
     out["rc"] = rc
     return out

@@ -38,6 +38,20 @@ template <> struct Plans<320> { using F = Plan<320, 16, 20, 4, 4>; using I = Pla
 template <> struct Plans<384> { using F = Plan<384, 16, 8, 8, 6>; using I = Plan<384, 16, 6, 8, 8>; };
 template <> struct Plans<512> { using F = Plan<512, 16, 8, 8, 8>; using I = Plan<512, 16, 8, 8, 8>; };
 
+// Alternative radix schedules (variant 1) with twice the lanes per transform
+// (fewer values per lane, more LDS hand-overs); a tuner may pick them per
+// image side and coil count.
+template <int N, int V> struct PlansV { using F = typename Plans<N>::F; using I = typename Plans<N>::I; };
+template <> struct PlansV<64, 1> { using F = Plan<64, 16, 4, 4, 4>; using I = Plan<64, 16, 4, 4, 4>; };
+template <> struct PlansV<128, 1> { using F = Plan<128, 16, 8, 4, 4>; using I = Plan<128, 16, 4, 4, 8>; };
+template <> struct PlansV<160, 1> { using F = Plan<160, 16, 10, 4, 4>; using I = Plan<160, 16, 4, 4, 10>; };
+template <> struct PlansV<192, 1> { using F = Plan<192, 16, 12, 4, 4>; using I = Plan<192, 16, 4, 4, 12>; };
+template <> struct PlansV<256, 1> { using F = Plan<256, 32, 8, 8, 4>; using I = Plan<256, 32, 4, 8, 8>; };
+template <> struct PlansV<320, 1> { using F = Plan<320, 32, 10, 4, 8>; using I = Plan<320, 32, 8, 4, 10>; };
+template <> struct PlansV<384, 1> { using F = Plan<384, 32, 12, 8, 4>; using I = Plan<384, 32, 4, 8, 12>; };
+template <> struct PlansV<512, 1> { using F = Plan<512, 32, 16, 4, 8>; using I = Plan<512, 32, 8, 4, 16>; };
+constexpr int kVariants = 2;
+
 // Plans of the one-pass phase-encode operator: fewer values per lane (more
 // lanes per transform) keep its four per-lane arrays within two waves per SIMD.
 template <int N> struct Plans1D { using F = typename Plans<N>::F; using I = typename Plans<N>::I; };
@@ -70,9 +84,14 @@ template <class F, class I, int WAVES = 4> struct PairGeo {
   static constexpr int CPW = 64 / T;      // columns per wave in column kernels
   static constexpr int COLS = WAVES * CPW;  // columns per column-kernel workgroup
 };
-template <int N> struct Geo : PairGeo<typename Plans<N>::F, typename Plans<N>::I> {
-  using F = typename Plans<N>::F;
-  using I = typename Plans<N>::I;
+template <int N> struct TwBlock;
+template <int N> struct TwBase;
+template <int N, int V = 0> struct Geo : PairGeo<typename PlansV<N, V>::F, typename PlansV<N, V>::I> {
+  using F = typename PlansV<N, V>::F;
+  using I = typename PlansV<N, V>::I;
+  // offsets of this geometry's forward / inverse twiddle tables in g_tw
+  static constexpr int TWF = TwBase<N>::v + (V == 0 ? TwBlock<N>::f : TwBlock<N>::fa);
+  static constexpr int TWI = TwBase<N>::v + (V == 0 ? TwBlock<N>::i : TwBlock<N>::ia);
 };
 // the phase-encode kernel's blocks span 16 columns (128 B of every row of a
 // coil map) so that no cache line of the streamed coil maps is split between
@@ -89,15 +108,16 @@ template <int N> struct Geo1D : PairGeo<typename Plans1D<N>::F, typename Plans1D
 };
 
 // Twiddle tables of every plan (TwLayout order), FP64-computed on the host and
-// rounded once to FP32; per image side N: [F][I][F 1-D][I 1-D].
+// rounded once to FP32; per image side N: [F][I][F 1-D][I 1-D][F alt][I alt].
 template <int N> struct TwBlock {
   static constexpr int f = 0;
   static constexpr int i = f + TwLayout<typename Plans<N>::F>::size();
   static constexpr int f1 = i + TwLayout<typename Plans<N>::I>::size();
   static constexpr int i1 = f1 + TwLayout<typename Plans1D<N>::F>::size();
-  static constexpr int size = i1 + TwLayout<typename Plans1D<N>::I>::size();
+  static constexpr int fa = i1 + TwLayout<typename Plans1D<N>::I>::size();
+  static constexpr int ia = fa + TwLayout<typename PlansV<N, 1>::F>::size();
+  static constexpr int size = ia + TwLayout<typename PlansV<N, 1>::I>::size();
 };
-template <int N> struct TwBase;
 template <> struct TwBase<64> { static constexpr int v = 0; };
 template <> struct TwBase<128> { static constexpr int v = TwBase<64>::v + TwBlock<64>::size; };
 template <> struct TwBase<160> { static constexpr int v = TwBase<128>::v + TwBlock<128>::size; };
@@ -137,14 +157,19 @@ template <class PL> __device__ __forceinline__ bool lay_out_ok(int j) {
 }
 
 // ---------------------------------------------------------------------------
-// Pass 1: t_c[s, y, :] = DFT_x(S_c[s, y, :] * x[s, y, :]); task = (s, y, c), c fastest.
+// Coil images: image ci of the coil-major buffers (coil maps, t, k-space) is
+// coil ci - cb[s] of slice s = cs[ci].  cb == nullptr means every slice has C
+// coils (ci = s * C + c); otherwise slice s owns images cb[s] .. cb[s+1]-1.
+
+// Pass 1: t_c[s, y, :] = DFT_x(S_c[s, y, :] * x[s, y, :]).  Uniform coil count:
+// task = (s, y, c), c fastest; per-slice coil counts: task = (ci, y).
 // A transform group is T consecutive lanes of one wave (wave-level hand-over).
-template <int N>
+template <int N, int V = 0>
 __global__ __launch_bounds__(256) void k_row_fwd(const float2 *__restrict__ x,
                                                  const float2 *__restrict__ sens,
                                                  float2 *__restrict__ t, int C, int tasks,
-                                                 int *k_inc) {
-  using Gm = Geo<N>;
+                                                 int *k_inc, const int *__restrict__ cs) {
+  using Gm = Geo<N, V>;
   using F = typename Gm::F;
   // the solver's iteration counter: advanced here, read by the step kernel of
   // the same iteration (stream order separates the two)
@@ -155,11 +180,20 @@ __global__ __launch_bounds__(256) void k_row_fwd(const float2 *__restrict__ x,
   const int g = threadIdx.x / T, j0 = threadIdx.x % T;
   const int task = blockIdx.x * Gm::G + g;
   const bool valid = task < tasks;
-  const int c = valid ? task % C : 0;
-  const int sy = valid ? task / C : 0;
-  const int s = sy / N, yy = sy % N;
-  const float2 *xr = x + (size_t)sy * N;
-  const float2 *sr = sens + ((size_t)(s * C + c) * N + yy) * N;
+  int s, yy, cim;
+  if (cs) {
+    cim = valid ? task / N : 0;
+    yy = valid ? task % N : 0;
+    s = cs[cim];
+  } else {
+    const int c = valid ? task % C : 0;
+    const int sy = valid ? task / C : 0;
+    s = sy / N;
+    yy = sy % N;
+    cim = s * C + c;
+  }
+  const float2 *xr = x + ((size_t)s * N + yy) * N;
+  const float2 *sr = sens + ((size_t)cim * N + yy) * N;
   float2 v[Gm::P];
 #pragma unroll
   for (int b = 0; b < F::NB_in; ++b) {
@@ -171,10 +205,10 @@ __global__ __launch_bounds__(256) void k_row_fwd(const float2 *__restrict__ x,
       v[b * F::R_in + r] = ok ? cmul(sr[i], xr[i]) : make_float2(0.f, 0.f);
     }
   }
-  load_tw(s_tw, TwBase<N>::v + TwBlock<N>::f, TwLayout<F>::size());
+  load_tw(s_tw, Gm::TWF, TwLayout<F>::size());
   __syncthreads();
   fft_run<F, -1>(v, s_buf[g], j0, s_tw);
-  float2 *tr = t + ((size_t)(s * C + c) * N + yy) * N;
+  float2 *tr = t + ((size_t)cim * N + yy) * N;
 #pragma unroll
   for (int b = 0; b < F::NB_out; ++b) {
     const int j = j0 + b * T;
@@ -194,12 +228,12 @@ template <int MASK1D> __device__ __forceinline__ bool sampled(const uint8_t *mas
   return MASK1D ? mask_s[ky] != 0 : mask_s[(size_t)ky * N + kx] != 0;
 }
 
-template <int N, int MODE, int MASK1D>
+template <int N, int MODE, int MASK1D, int V = 0>
 __global__ __launch_bounds__(256, 2) void k_col(float2 *__restrict__ t, const float2 *__restrict__ kin,
                                              float2 *__restrict__ kout, const uint8_t *__restrict__ mask,
                                              int C, float a_scale, float b_scale,
-                                             double *__restrict__ partials) {
-  using Gm = Geo<N>;
+                                             double *__restrict__ partials, const int *__restrict__ cs) {
+  using Gm = Geo<N, V>;
   using F = typename Gm::F;
   using I = typename Gm::I;
   constexpr int T = Gm::T;
@@ -213,7 +247,7 @@ __global__ __launch_bounds__(256, 2) void k_col(float2 *__restrict__ t, const fl
   float2 *bufc = s_buf + wv * Gm::CPW * Gm::LDSN + ci;
   const int kx = blockIdx.x * Gm::COLS + col;
   const int sc = blockIdx.y;
-  const int s = sc / C;
+  const int s = cs ? cs[sc] : sc / C;
   const uint8_t *mask_s = MASK1D ? mask + (size_t)s * N : mask + (size_t)s * N * N;
   float2 *tc = t + (size_t)sc * N * N;
   float2 v[Gm::P];
@@ -240,7 +274,7 @@ __global__ __launch_bounds__(256, 2) void k_col(float2 *__restrict__ t, const fl
         v[b * I::R_in + r] = ((mbits >> (b * I::R_in + r)) & 1u) ? kc[(size_t)ky * N + kx] : make_float2(0.f, 0.f);
       }
     }
-    load_tw(s_twI, TwBase<N>::v + TwBlock<N>::i, TwLayout<I>::size());
+    load_tw(s_twI, Gm::TWI, TwLayout<I>::size());
     __syncthreads();
   } else {
 #pragma unroll
@@ -253,8 +287,8 @@ __global__ __launch_bounds__(256, 2) void k_col(float2 *__restrict__ t, const fl
         v[b * F::R_in + r] = ok ? tc[(size_t)yy * N + kx] : make_float2(0.f, 0.f);
       }
     }
-    load_tw(s_twF, TwBase<N>::v + TwBlock<N>::f, TwLayout<F>::size());
-    if constexpr (MODE == COL_NORMAL) load_tw(s_twI, TwBase<N>::v + TwBlock<N>::i, TwLayout<I>::size());
+    load_tw(s_twF, Gm::TWF, TwLayout<F>::size());
+    if constexpr (MODE == COL_NORMAL) load_tw(s_twI, Gm::TWI, TwLayout<I>::size());
     __syncthreads();
     fft_run<F, -1, Gm::CPW>(v, bufc, j0, s_twF);
 #pragma unroll
@@ -308,12 +342,13 @@ __global__ __launch_bounds__(256, 2) void k_col(float2 *__restrict__ t, const fl
 // Pass 3: y[s, r, :] = alpha sum_c conj(S_c[s, r, :]) IDFT_x(t_c[s, r, :]) + beta w.
 // Block = rpw rows; transform group g handles row (g % rpw) and coils
 // g / rpw, g / rpw + G / rpw, ...; the groups are summed in a fixed order.
-template <int N>
+template <int N, int V = 0>
 __global__ __launch_bounds__(256, 2) void k_row_inv(const float2 *__restrict__ t,
                                                  const float2 *__restrict__ sens,
                                                  float2 *__restrict__ y, const float2 *w, float alpha,
-                                                 float beta, int C, int rows, int rpw) {
-  using Gm = Geo<N>;
+                                                 float beta, int C, int rows, int rpw,
+                                                 const int *__restrict__ cb) {
+  using Gm = Geo<N, V>;
   using I = typename Gm::I;
   constexpr int T = Gm::T;
   constexpr int G = Gm::G;
@@ -324,14 +359,17 @@ __global__ __launch_bounds__(256, 2) void k_row_inv(const float2 *__restrict__ t
   const int row = blockIdx.x * rpw + ro;
   const bool rvalid = row < rows;
   const int s = rvalid ? row / N : 0, yy = rvalid ? row % N : 0;
+  // this slice's coil images (every row of a block lies in one slice: rpw divides N)
+  const int cbase = cb ? cb[s] : s * C;
+  const int Cs = cb ? cb[s + 1] - cbase : C;
   float2 acc[Gm::P_IN];
 #pragma unroll
   for (int i = 0; i < Gm::P_IN; ++i) acc[i] = make_float2(0.f, 0.f);
-  const int iters = (C + cstep - 1) / cstep;
+  const int iters = (Cs + cstep - 1) / cstep;
   for (int it = 0; it < iters; ++it) {
     const int c = cg + it * cstep;
-    const bool valid = rvalid && c < C;
-    const size_t off = ((size_t)(s * C + (valid ? c : 0)) * N + yy) * N;
+    const bool valid = rvalid && c < Cs;
+    const size_t off = ((size_t)(cbase + (valid ? c : 0)) * N + yy) * N;
     const float2 *tr = t + off;
     const float2 *sr = sens + off;
     float2 v[Gm::P], sv[Gm::P_IN];
@@ -350,7 +388,7 @@ __global__ __launch_bounds__(256, 2) void k_row_inv(const float2 *__restrict__ t
       for (int r = 0; r < I::R_out; ++r) sv[b * I::R_out + r] = ok ? sr[j + r * I::B_out] : make_float2(0.f, 0.f);
     }
     if (it == 0) {
-      load_tw(s_tw, TwBase<N>::v + TwBlock<N>::i, TwLayout<I>::size());
+      load_tw(s_tw, Gm::TWI, TwLayout<I>::size());
       __syncthreads();
     }
     fft_run<I, +1>(v, s_buf[opaque(g)], opaque(j0), s_tw);
@@ -388,11 +426,12 @@ __global__ __launch_bounds__(256, 2) void k_row_inv(const float2 *__restrict__ t
 //   y[s, r, :] = alpha sum_c conj(S_c) IDFT_x(t_c[s, r, :]) + beta w[s, r, :]
 //   t_c[s, r, :] = DFT_x(S_c[s, r, :] y[s, r, :])            (in place)
 // The row's coil maps are read once for both halves.
-template <int N>
+template <int N, int V = 0>
 __global__ __launch_bounds__(256, 2) void k_row_inv_fwd(float2 *__restrict__ t, const float2 *__restrict__ sens,
                                                         float2 *__restrict__ y, const float2 *w, float alpha,
-                                                        float beta, int C, int rows, int rpw) {
-  using Gm = Geo<N>;
+                                                        float beta, int C, int rows, int rpw,
+                                                        const int *__restrict__ cb) {
+  using Gm = Geo<N, V>;
   using F = typename Gm::F;
   using I = typename Gm::I;
   constexpr int T = Gm::T;
@@ -406,14 +445,16 @@ __global__ __launch_bounds__(256, 2) void k_row_inv_fwd(float2 *__restrict__ t, 
   const int row = blockIdx.x * rpw + ro;
   const bool rvalid = row < rows;
   const int s = rvalid ? row / N : 0, yy = rvalid ? row % N : 0;
+  const int cbase = cb ? cb[s] : s * C;
+  const int Cs = cb ? cb[s + 1] - cbase : C;
   float2 acc[Gm::P_IN], sv[Gm::P_IN];
 #pragma unroll
   for (int i = 0; i < Gm::P_IN; ++i) acc[i] = make_float2(0.f, 0.f);
-  const int iters = (C + cstep - 1) / cstep;
+  const int iters = (Cs + cstep - 1) / cstep;
   for (int it = 0; it < iters; ++it) {
     const int c = cg + it * cstep;
-    const bool valid = rvalid && c < C;
-    const size_t off = ((size_t)(s * C + (valid ? c : 0)) * N + yy) * N;
+    const bool valid = rvalid && c < Cs;
+    const size_t off = ((size_t)(cbase + (valid ? c : 0)) * N + yy) * N;
     const float2 *tr = t + off;
     const float2 *sr = sens + off;
     float2 v[Gm::P];
@@ -432,8 +473,8 @@ __global__ __launch_bounds__(256, 2) void k_row_inv_fwd(float2 *__restrict__ t, 
       for (int r = 0; r < I::R_out; ++r) sv[b * I::R_out + r] = ok ? sr[j + r * I::B_out] : make_float2(0.f, 0.f);
     }
     if (it == 0) {
-      load_tw(s_twI, TwBase<N>::v + TwBlock<N>::i, TwLayout<I>::size());
-      load_tw(s_twF, TwBase<N>::v + TwBlock<N>::f, TwLayout<F>::size());
+      load_tw(s_twI, Gm::TWI, TwLayout<I>::size());
+      load_tw(s_twF, Gm::TWF, TwLayout<F>::size());
       __syncthreads();
     }
     fft_run<I, +1>(v, s_buf[opaque(g)], opaque(j0), s_twI);
@@ -476,8 +517,8 @@ __global__ __launch_bounds__(256, 2) void k_row_inv_fwd(float2 *__restrict__ t, 
   __syncthreads();
   for (int it = 0; it < iters; ++it) {
     const int c = cg + it * cstep;
-    const bool valid = rvalid && c < C;
-    const size_t off = ((size_t)(s * C + (valid ? c : 0)) * N + yy) * N;
+    const bool valid = rvalid && c < Cs;
+    const size_t off = ((size_t)(cbase + (valid ? c : 0)) * N + yy) * N;
     if (iters > 1) {
       const float2 *sr = sens + off;
 #pragma unroll
@@ -692,11 +733,14 @@ __device__ __forceinline__ float2 haar_levels(float2 ll, int tx, int ty, float l
 template <int LEVELS>
 __global__ __launch_bounds__(64) void k_step(const float2 *__restrict__ z, const float2 *__restrict__ pg,
                                              const float2 *x_old, float2 *x_new, float2 *z_new,
-                                             float pg_scale, float lam, float beta_arg,
+                                             float pg_scale, float lam_arg, float beta_arg,
                                              const int *__restrict__ k_dev, int use_k, int N,
-                                             double *__restrict__ partials) {
+                                             double *__restrict__ partials,
+                                             const float *__restrict__ lam_s) {
   const int lane = threadIdx.x, tx = lane & 7, ty = lane >> 3;
   const int s = blockIdx.z;
+  // per-slice threshold when a table is given
+  const float lam = lam_s ? lam_s[s] : lam_arg;
   const int px = blockIdx.x * 16 + 2 * tx, py = blockIdx.y * 16 + 2 * ty;
   const size_t o0 = (size_t)s * N * N + (size_t)py * N + px, o1 = o0 + N;
   // unconditional scalar load: its latency overlaps the vector loads below
@@ -760,6 +804,24 @@ __global__ __launch_bounds__(64) void k_reduce(const double *__restrict__ partia
     if (threadIdx.x == 0) out[c] = v;
   }
   if (threadIdx.x == 0 && k_dev) *k_dev = *k_dev + 1;
+}
+
+// Per-segment version of k_reduce, one wave per segment (blockIdx.x): segment s
+// covers partials [cb[s] * len, cb[s+1] * len) if cb is given, else
+// [s * len, (s+1) * len), in units of `width`-tuples; out[s * width + c].
+__global__ __launch_bounds__(64) void k_reduce_seg(const double *__restrict__ partials,
+                                                   const int *__restrict__ cb, int len, int width,
+                                                   double *__restrict__ out) {
+  const int s = blockIdx.x;
+  const int b = cb ? cb[s] * len : s * len;
+  const int e = cb ? cb[s + 1] * len : (s + 1) * len;
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = b + threadIdx.x; i < e; i += 64)
+    for (int c = 0; c < width && c < 4; ++c) a[c] += partials[(size_t)i * width + c];
+  for (int c = 0; c < width && c < 4; ++c) {
+    const double v = wave_sum_d(a[c]);
+    if (threadIdx.x == 0) out[(size_t)s * width + c] = v;
+  }
 }
 
 // FP64 partial sums of |v|^2 (grid-stride), one value per block

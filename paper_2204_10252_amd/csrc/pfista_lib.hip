@@ -86,6 +86,8 @@ template <int N> void fill_n(std::vector<float2> &h) {
   fill_plan_tw<typename pf::Plans<N>::I>(h, b + pf::TwBlock<N>::i);
   fill_plan_tw<typename pf::Plans1D<N>::F>(h, b + pf::TwBlock<N>::f1);
   fill_plan_tw<typename pf::Plans1D<N>::I>(h, b + pf::TwBlock<N>::i1);
+  fill_plan_tw<typename pf::PlansV<N, 1>::F>(h, b + pf::TwBlock<N>::fa);
+  fill_plan_tw<typename pf::PlansV<N, 1>::I>(h, b + pf::TwBlock<N>::ia);
 }
 
 int ensure_twiddles() {
@@ -184,51 +186,84 @@ unsigned blocks_for(size_t n) {
 }
 
 // ------------------------------------------------------------------ per-N dispatch
-template <int N> struct Ops {
-  using Gm = pf::Geo<N>;
+// What a launch needs to know about the slices it covers.  A plan's slices all
+// have `coils` coils (cb = cs = nullptr); a batch group's slices may differ, and
+// then cb (device, slices + 1 entries) holds the first coil image of every
+// slice and cs (device, one entry per coil image) the slice of every image.
+struct Shape {
+  int slices;
+  int coils;        // coil count when uniform
+  int images;       // coil images in all
+  int haar_levels;
+  int mask_kind;
+  const int *cb;
+  const int *cs;
+  int cmin;         // smallest coil count of a slice (sizes the coil-combine passes)
+  int rpw_mult;     // rows per coil-combine block, as a multiple of the default
+  int fused;        // fuse the row passes between the applies of a chain
+};
 
-  static void row_fwd(const pfista_desc &d, const float2 *x, const float2 *sens, float2 *t, hipStream_t st,
+Shape shape_of(const pfista_desc &d) {
+  return Shape{d.slices, d.coils, d.slices * d.coils, d.haar_levels, d.mask_kind, nullptr, nullptr, d.coils, 1, 1};
+}
+
+template <int N, int V = 0> struct Ops {
+  using Gm = pf::Geo<N, V>;
+
+  static void row_fwd(const Shape &d, const float2 *x, const float2 *sens, float2 *t, hipStream_t st,
                       int *k_inc = nullptr) {
-    const int tasks = d.slices * N * d.coils;
+    const int tasks = d.images * N;
     const int grid = (tasks + Gm::G - 1) / Gm::G;
-    pf::k_row_fwd<N><<<grid, Gm::THREADS, 0, st>>>(x, sens, t, d.coils, tasks, k_inc);
+    pf::k_row_fwd<N, V><<<grid, Gm::THREADS, 0, st>>>(x, sens, t, d.coils, tasks, k_inc, d.cs);
   }
 
   template <int MODE>
-  static void col(const pfista_desc &d, float2 *t, const float2 *kin, float2 *kout, const uint8_t *mask,
+  static void col(const Shape &d, float2 *t, const float2 *kin, float2 *kout, const uint8_t *mask,
                   float a, float b, double *partials, hipStream_t st) {
-    const dim3 grid(N / Gm::COLS, d.slices * d.coils);
-    if (d.mask_kind == PFISTA_MASK_1D)
-      pf::k_col<N, MODE, 1><<<grid, Gm::THREADS, 0, st>>>(t, kin, kout, mask, d.coils, a, b, partials);
-    else
-      pf::k_col<N, MODE, 0><<<grid, Gm::THREADS, 0, st>>>(t, kin, kout, mask, d.coils, a, b, partials);
+    const dim3 grid(N / Gm::COLS, d.images);
+    if constexpr (V == 0) {
+      if (d.mask_kind == PFISTA_MASK_1D) {
+        pf::k_col<N, MODE, 1, V><<<grid, Gm::THREADS, 0, st>>>(t, kin, kout, mask, d.coils, a, b, partials, d.cs);
+        return;
+      }
+    }
+    pf::k_col<N, MODE, 0, V><<<grid, Gm::THREADS, 0, st>>>(t, kin, kout, mask, d.coils, a, b, partials, d.cs);
   }
 
-  static void row_inv(const pfista_desc &d, const float2 *t, const float2 *sens, float2 *y, const float2 *w,
+  // rows per block of the coil-combine passes: by default the largest power of
+  // two that leaves at least two coil groups per coil of a row (each block's
+  // transform groups split as rows x coil groups), times the tuner's multiple
+  static int rows_per_block(const Shape &d) {
+    int rpw = 1;
+    while (rpw * 2 * d.cmin <= Gm::G) rpw *= 2;
+    for (int m = d.rpw_mult; m > 1 && rpw < Gm::G; m /= 2) rpw *= 2;
+    return rpw;
+  }
+
+  static void row_inv(const Shape &d, const float2 *t, const float2 *sens, float2 *y, const float2 *w,
                       float alpha, float beta, hipStream_t st) {
-    int rpw = 1;
-    while (rpw * 2 * d.coils <= Gm::G) rpw *= 2;
+    const int rpw = rows_per_block(d);
     const int rows = d.slices * N;
     const int grid = (rows + rpw - 1) / rpw;
-    pf::k_row_inv<N><<<grid, Gm::THREADS, 0, st>>>(t, sens, y, w, alpha, beta, d.coils, rows, rpw);
+    pf::k_row_inv<N, V><<<grid, Gm::THREADS, 0, st>>>(t, sens, y, w, alpha, beta, d.coils, rows, rpw, d.cb);
   }
 
-  static void row_inv_fwd(const pfista_desc &d, float2 *t, const float2 *sens, float2 *y, const float2 *w,
+  static void row_inv_fwd(const Shape &d, float2 *t, const float2 *sens, float2 *y, const float2 *w,
                           float alpha, float beta, hipStream_t st) {
-    int rpw = 1;
-    while (rpw * 2 * d.coils <= Gm::G) rpw *= 2;
+    const int rpw = rows_per_block(d);
     const int rows = d.slices * N;
     const int grid = (rows + rpw - 1) / rpw;
-    pf::k_row_inv_fwd<N><<<grid, Gm::THREADS, 0, st>>>(t, sens, y, w, alpha, beta, d.coils, rows, rpw);
+    pf::k_row_inv_fwd<N, V><<<grid, Gm::THREADS, 0, st>>>(t, sens, y, w, alpha, beta, d.coils, rows, rpw, d.cb);
   }
 
   // A chain of m normal applies in which apply k+1's input is apply k's output:
   //   y_k = alpha_k A^H A y_{k-1} + beta_k w_k,  y_0 = x.
-  // For a 2-D mask the row passes between applies are fused (2m + 1 kernels).
-  static void chain(const pfista_desc &d, const float2 *sens, const uint8_t *mask, const float2 *x, int m,
+  // For a 2-D mask the row passes between applies are fused (2m + 1 kernels)
+  // unless the shape asks for separate passes (3m kernels).
+  static void chain(const Shape &d, const float2 *sens, const uint8_t *mask, const float2 *x, int m,
                     const float *alpha, const float *beta, const float2 *const *w, float2 *const *y, float2 *t,
                     hipStream_t st, int *k_inc) {
-    if (d.mask_kind == PFISTA_MASK_1D) {
+    if (d.mask_kind == PFISTA_MASK_1D || !d.fused) {
       const float2 *src = x;
       for (int k = 0; k < m; ++k) {
         normal(d, sens, mask, src, y[k], alpha[k], w[k], beta[k], t, st, k == 0 ? k_inc : nullptr);
@@ -247,27 +282,31 @@ template <int N> struct Ops {
     }
   }
 
-  static void normal(const pfista_desc &d, const float2 *sens, const uint8_t *mask, const float2 *x, float2 *y,
+  static void normal(const Shape &d, const float2 *sens, const uint8_t *mask, const float2 *x, float2 *y,
                      float alpha, const float2 *w, float beta, float2 *t, hipStream_t st, int *k_inc = nullptr) {
-    if (d.mask_kind == PFISTA_MASK_1D) {
-      using G1 = pf::Geo1D<N>;
-      const dim3 grid(N / G1::COLS, d.slices);
-      pf::k_normal_1d<N><<<grid, G1::THREADS, 0, st>>>(x, sens, mask, y, w, alpha / (float)N, beta, d.coils, k_inc);
-      return;
+    if constexpr (V == 0) {
+      if (d.mask_kind == PFISTA_MASK_1D) {
+        using G1 = pf::Geo1D<N>;
+        const dim3 grid(N / G1::COLS, d.slices);
+        pf::k_normal_1d<N><<<grid, G1::THREADS, 0, st>>>(x, sens, mask, y, w, alpha / (float)N, beta, d.coils, k_inc);
+        return;
+      }
     }
     row_fwd(d, x, sens, t, st, k_inc);
     col<pf::COL_NORMAL>(d, t, nullptr, nullptr, mask, 1.f, 0.f, nullptr, st);
     row_inv(d, t, sens, y, w, (float)((double)alpha / ((double)N * N)), beta, st);
   }
 
-  // number of FP64 partial sums the residual column pass writes
-  static int resid_blocks(const pfista_desc &d) { return (N / Gm::COLS) * d.slices * d.coils; }
+  // FP64 partial sums the residual column pass writes: N / COLS per coil image,
+  // image-major
+  static int resid_per_image() { return N / Gm::COLS; }
+  static int resid_blocks(const Shape &d) { return resid_per_image() * d.images; }
 
   // kernel passes timed by pfista_profile_normal: the three passes of one apply
   // and the fused inverse+forward row pass of the Horner chain (2-D mask), or
   // the single phase-encode pass; `pass` launches pass k alone
-  static int passes(const pfista_desc &d) { return d.mask_kind == PFISTA_MASK_1D ? 1 : 4; }
-  static void pass(int k, const pfista_desc &d, const float2 *sens, const uint8_t *mask, const float2 *x, float2 *y,
+  static int passes(const Shape &d) { return d.mask_kind == PFISTA_MASK_1D ? 1 : 4; }
+  static void pass(int k, const Shape &d, const float2 *sens, const uint8_t *mask, const float2 *x, float2 *y,
                    float alpha, const float2 *w, float beta, float2 *t, hipStream_t st) {
     if (d.mask_kind == PFISTA_MASK_1D) {
       normal(d, sens, mask, x, y, alpha, w, beta, t, st);
@@ -282,35 +321,36 @@ template <int N> struct Ops {
     }
   }
 
-  static void forward(const pfista_desc &d, const float2 *sens, const uint8_t *mask, const float2 *x,
+  static void forward(const Shape &d, const float2 *sens, const uint8_t *mask, const float2 *x,
                       float2 *kout, float2 *t, hipStream_t st) {
     row_fwd(d, x, sens, t, st);
     col<pf::COL_FWD_OUT>(d, t, nullptr, kout, mask, (float)(1.0 / N), 0.f, nullptr, st);
   }
 
-  static void adjoint(const pfista_desc &d, const float2 *sens, const uint8_t *mask, const float2 *kin,
+  static void adjoint(const Shape &d, const float2 *sens, const uint8_t *mask, const float2 *kin,
                       float2 *y, float alpha, float2 *t, hipStream_t st) {
     col<pf::COL_ADJ_IN>(d, t, kin, nullptr, mask, 1.f, 0.f, nullptr, st);
     row_inv(d, t, sens, y, nullptr, (float)((double)alpha / N), 0.f, st);
   }
 
-  // partial sums of |a M F S x - b_scale b|^2, (N/16)*S*C of them
-  static void resid(const pfista_desc &d, const float2 *sens, const uint8_t *mask, const float2 *x,
+  // partial sums of |a M F S x - b_scale b|^2, resid_blocks(d) of them
+  static void resid(const Shape &d, const float2 *sens, const uint8_t *mask, const float2 *x,
                     const float2 *b, double a, double b_scale, float2 *t, double *partials, hipStream_t st) {
     row_fwd(d, x, sens, t, st);
     col<pf::COL_RESID>(d, t, b, nullptr, mask, (float)(a / N), (float)b_scale, partials, st);
   }
 
-  // k_dev: a valid device int; use_k != 0 takes beta = k / (k + 3) from it
-  static void step(const pfista_desc &d, const float2 *z, const float2 *pg, const float2 *xo, float2 *xn,
+  // k_dev: a valid device int; use_k != 0 takes beta = k / (k + 3) from it;
+  // lam_s: per-slice thresholds (device) or nullptr for `lam`
+  static void step(const Shape &d, const float2 *z, const float2 *pg, const float2 *xo, float2 *xn,
                    float2 *zn, float pg_scale, float lam, float beta, const int *k_dev, int use_k,
-                   double *partials, hipStream_t st) {
+                   double *partials, hipStream_t st, const float *lam_s = nullptr) {
     const dim3 grid(N / 16, N / 16, d.slices);
     switch (d.haar_levels) {
-      case 1: pf::k_step<1><<<grid, 64, 0, st>>>(z, pg, xo, xn, zn, pg_scale, lam, beta, k_dev, use_k, N, partials); break;
-      case 2: pf::k_step<2><<<grid, 64, 0, st>>>(z, pg, xo, xn, zn, pg_scale, lam, beta, k_dev, use_k, N, partials); break;
-      case 3: pf::k_step<3><<<grid, 64, 0, st>>>(z, pg, xo, xn, zn, pg_scale, lam, beta, k_dev, use_k, N, partials); break;
-      default: pf::k_step<4><<<grid, 64, 0, st>>>(z, pg, xo, xn, zn, pg_scale, lam, beta, k_dev, use_k, N, partials); break;
+      case 1: pf::k_step<1><<<grid, 64, 0, st>>>(z, pg, xo, xn, zn, pg_scale, lam, beta, k_dev, use_k, N, partials, lam_s); break;
+      case 2: pf::k_step<2><<<grid, 64, 0, st>>>(z, pg, xo, xn, zn, pg_scale, lam, beta, k_dev, use_k, N, partials, lam_s); break;
+      case 3: pf::k_step<3><<<grid, 64, 0, st>>>(z, pg, xo, xn, zn, pg_scale, lam, beta, k_dev, use_k, N, partials, lam_s); break;
+      default: pf::k_step<4><<<grid, 64, 0, st>>>(z, pg, xo, xn, zn, pg_scale, lam, beta, k_dev, use_k, N, partials, lam_s); break;
     }
   }
 };
@@ -329,6 +369,31 @@ template <int N> struct Ops {
     default: break;                            \
   }
 
+// calls the statement with NN = n and VV = v (radix-schedule variant 0 or 1)
+#define PF_VCASE(NV, v, ...)                 \
+  case NV: {                                 \
+    constexpr int NN = NV;                   \
+    if (v) {                                 \
+      constexpr int VV = 1;                  \
+      __VA_ARGS__;                           \
+    } else {                                 \
+      constexpr int VV = 0;                  \
+      __VA_ARGS__;                           \
+    }                                        \
+  } break;
+#define PF_DISPATCH_V(n, v, ...)             \
+  switch (n) {                               \
+    PF_VCASE(64, v, __VA_ARGS__)             \
+    PF_VCASE(128, v, __VA_ARGS__)            \
+    PF_VCASE(160, v, __VA_ARGS__)            \
+    PF_VCASE(192, v, __VA_ARGS__)            \
+    PF_VCASE(256, v, __VA_ARGS__)            \
+    PF_VCASE(320, v, __VA_ARGS__)            \
+    PF_VCASE(384, v, __VA_ARGS__)            \
+    PF_VCASE(512, v, __VA_ARGS__)            \
+    default: break;                          \
+  }
+
 const float2 *F2(const pfista_c32 *p) { return reinterpret_cast<const float2 *>(p); }
 float2 *F2(pfista_c32 *p) { return reinterpret_cast<float2 *>(p); }
 
@@ -336,7 +401,7 @@ void normal_op(const pfista_desc &d, const pfista_c32 *sens, const uint8_t *mask
                float alpha, const float2 *w, float beta, void *ws, hipStream_t st, int *k_inc = nullptr) {
   const Layout L = layout(d);
   float2 *t = at<float2>(ws, L.t);
-  PF_DISPATCH(d.n, Ops<NN>::normal(d, F2(sens), mask, x, y, alpha, w, beta, t, st, k_inc));
+  PF_DISPATCH(d.n, Ops<NN>::normal(shape_of(d), F2(sens), mask, x, y, alpha, w, beta, t, st, k_inc));
 }
 
 void reduce(const double *partials, int count, int width, double *out, int *k_dev, hipStream_t st) {
@@ -353,30 +418,46 @@ void norm2_dev(const float2 *v, size_t n, double *partials, double *out, hipStre
 // h = c_d g; h = c_i g + N' h for i = d-1 .. 0.  The first apply folds c_d
 // into its alpha; optionally preceded by the gradient apply g = N' z - A'^H b'
 // (then `pre_x` = z, `pre_w` = A'^H b', output in g), all as one chain.
+// The applies of one gradient + polynomial chain: with `pre_x`, first the
+// gradient g = inv_l A^H A pre_x - pre_w, then the Horner recursion of the
+// nested form c0 I + N'(c1 I + N'(... c_d I)): h = c_d g; h = c_i g + N' h for
+// i = d-1 .. 0 (the first apply folds c_d into its alpha), output in `out`.
+struct Chain {
+  int m = 0;
+  float alpha[kMaxDegree + 1], beta[kMaxDegree + 1];
+  const float2 *w[kMaxDegree + 1];
+  float2 *y[kMaxDegree + 1];
+  const float2 *x0 = nullptr;
+};
+
+Chain make_chain(double inv_l, const std::vector<double> &c, const float2 *pre_x, const float2 *pre_w, float2 *g,
+                 float2 *out) {
+  Chain ch;
+  const int deg = (int)c.size() - 1;
+  if (pre_x) {
+    ch.alpha[ch.m] = (float)inv_l; ch.beta[ch.m] = -1.f; ch.w[ch.m] = pre_w; ch.y[ch.m] = g; ++ch.m;
+  }
+  for (int i = 1; i <= deg; ++i) {
+    ch.alpha[ch.m] = (float)(i == 1 ? c[deg] * inv_l : inv_l);
+    ch.beta[ch.m] = (float)c[deg - i];
+    ch.w[ch.m] = g;
+    ch.y[ch.m] = out;
+    ++ch.m;
+  }
+  ch.x0 = pre_x ? pre_x : g;
+  return ch;
+}
+
 void grad_poly_op(const pfista_desc &d, const pfista_c32 *sens, const uint8_t *mask, double inv_l,
                   const std::vector<double> &c, const float2 *pre_x, const float2 *pre_w, float2 *g,
                   float2 *out, void *ws, hipStream_t st, int *k_inc) {
   const int deg = (int)c.size() - 1;
   const Layout L = layout(d);
   float2 *t = at<float2>(ws, L.t);
-  float alpha[kMaxDegree + 1], beta[kMaxDegree + 1];
-  const float2 *w[kMaxDegree + 1];
-  float2 *y[kMaxDegree + 1];
-  int m = 0;
-  if (pre_x) {
-    alpha[m] = (float)inv_l; beta[m] = -1.f; w[m] = pre_w; y[m] = g; ++m;
-  }
-  for (int i = 1; i <= deg; ++i) {
-    alpha[m] = (float)(i == 1 ? c[deg] * inv_l : inv_l);
-    beta[m] = (float)c[deg - i];
-    w[m] = g;
-    y[m] = out;
-    ++m;
-  }
-  if (m > 0) {
-    const float2 *x0 = pre_x ? pre_x : g;
-    PF_DISPATCH(d.n, Ops<NN>::chain(d, F2(sens), mask, x0, m, alpha, beta, w, y, t, st, k_inc));
-  }
+  const Chain ch = make_chain(inv_l, c, pre_x, pre_w, g, out);
+  if (ch.m > 0)
+    PF_DISPATCH(d.n, Ops<NN>::chain(shape_of(d), F2(sens), mask, ch.x0, ch.m, ch.alpha, ch.beta, ch.w, ch.y, t, st,
+                                    k_inc));
   if (deg == 0 && !pre_x) pf::k_scale<<<blocks_for(L.n_img), 256, 0, st>>>(g, out, L.n_img, (float)c[0]);
 }
 
@@ -567,7 +648,7 @@ int pfista_step(const pfista_plan *p, const pfista_c32 *z, const pfista_c32 *pg,
   if (L.n_img == 0) return PFISTA_OK;
   double *partials = at<double>(ws, L.partials);
   DevState *ds = at<DevState>(ws, L.state);
-  PF_DISPATCH(p->d.n, Ops<NN>::step(p->d, F2(z), F2(pg), F2(x_old), F2(x_new), F2(z_new), 1.f, lambda, beta_k,
+  PF_DISPATCH(p->d.n, Ops<NN>::step(shape_of(p->d), F2(z), F2(pg), F2(x_old), F2(x_new), F2(z_new), 1.f, lambda, beta_k,
                                     &ds->k, 0, partials, stream));
   const int nblk = (p->d.n / 16) * (p->d.n / 16) * p->d.slices;
   reduce(partials, nblk, 3, red, nullptr, stream);
@@ -583,7 +664,7 @@ int pfista_forward(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *
   const Layout L = layout(p->d);
   if (L.n_img == 0) return PFISTA_OK;
   float2 *t = at<float2>(ws, L.t);
-  PF_DISPATCH(p->d.n, Ops<NN>::forward(p->d, F2(sens), mask, F2(x), F2(kspace), t, stream));
+  PF_DISPATCH(p->d.n, Ops<NN>::forward(shape_of(p->d), F2(sens), mask, F2(x), F2(kspace), t, stream));
   return launch_status("pfista_forward");
 }
 
@@ -596,7 +677,7 @@ int pfista_adjoint(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *
   const Layout L = layout(p->d);
   if (L.n_img == 0) return PFISTA_OK;
   float2 *t = at<float2>(ws, L.t);
-  PF_DISPATCH(p->d.n, Ops<NN>::adjoint(p->d, F2(sens), mask, F2(kspace), F2(y), alpha, t, stream));
+  PF_DISPATCH(p->d.n, Ops<NN>::adjoint(shape_of(p->d), F2(sens), mask, F2(kspace), F2(y), alpha, t, stream));
   return launch_status("pfista_adjoint");
 }
 
@@ -619,10 +700,10 @@ int pfista_data_term(const pfista_plan *p, const pfista_c32 *sens, const uint8_t
   float2 *t = at<float2>(ws, L.t);
   double *partials = at<double>(ws, L.partials);
   DevState *ds = at<DevState>(ws, L.state);
-  PF_DISPATCH(p->d.n, Ops<NN>::resid(p->d, F2(sens), mask, F2(x), F2(b), std::sqrt(inv_l), b_scale, t, partials,
+  PF_DISPATCH(p->d.n, Ops<NN>::resid(shape_of(p->d), F2(sens), mask, F2(x), F2(b), std::sqrt(inv_l), b_scale, t, partials,
                                      stream));
   int cnt = 0;
-  PF_DISPATCH(p->d.n, cnt = Ops<NN>::resid_blocks(p->d));
+  PF_DISPATCH(p->d.n, cnt = Ops<NN>::resid_blocks(shape_of(p->d)));
   reduce(partials, cnt, 1, ds->data, nullptr, stream);
   PF_TRY(launch_status("pfista_data_term"));
   double h = 0.0;
@@ -677,7 +758,7 @@ int pfista_profile_normal(const pfista_plan *p, const pfista_c32 *sens, const ui
   if (reps < 1) return fail(PFISTA_EINVAL, "reps must be >= 1");
   const pfista_desc &d = p->d;
   int np = 0;
-  PF_DISPATCH(d.n, np = Ops<NN>::passes(d));
+  PF_DISPATCH(d.n, np = Ops<NN>::passes(shape_of(d)));
   *npasses = np;
   for (int k = 0; k < np; ++k) pass_ms[k] = 0.f;
   if (d.slices == 0) return PFISTA_OK;
@@ -696,7 +777,7 @@ int pfista_profile_normal(const pfista_plan *p, const pfista_c32 *sens, const ui
   for (int k = 0; k < np && rc == PFISTA_OK; ++k) {
     hipError_t he = hipEventRecord(e0, stream);
     for (int r = 0; r < reps && he == hipSuccess; ++r)
-      PF_DISPATCH(d.n, Ops<NN>::pass(k, d, F2(sens), mask, F2(x), F2(y), 1.f, nullptr, 0.f, t, stream));
+      PF_DISPATCH(d.n, Ops<NN>::pass(k, shape_of(d), F2(sens), mask, F2(x), F2(y), 1.f, nullptr, 0.f, t, stream));
     if (he == hipSuccess) he = hipEventRecord(e1, stream);
     if (he == hipSuccess) he = hipEventSynchronize(e1);
     float ms = 0.f;
@@ -783,7 +864,7 @@ int pfista_solve(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *ma
     if (rep) *rep = r;
     return PFISTA_OK;
   }
-  PF_DISPATCH(d.n, Ops<NN>::adjoint(d, F2(sens), mask, F2(b), ahb, (float)(std::sqrt(inv_l) / bnorm),
+  PF_DISPATCH(d.n, Ops<NN>::adjoint(shape_of(d), F2(sens), mask, F2(b), ahb, (float)(std::sqrt(inv_l) / bnorm),
                                     at<float2>(ws, L.t), stream));
   if (prm->k0 == 0) {
     pf::k_fill<<<blocks_for(L.n_img), 256, 0, stream>>>(x, L.n_img, make_float2(0.f, 0.f));
@@ -805,7 +886,7 @@ int pfista_solve(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *ma
     const float pg_scale = deg == 0 ? (float)c[0] : 1.f;
     // momentum off (Algorithms 1 and 3): beta = 0, so z_(k+1) = x_(k+1)
     const int use_k = prm->momentum ? 1 : 0;
-    PF_DISPATCH(d.n, Ops<NN>::step(d, zb, pg, x, x, zb, pg_scale, lam, 0.f, &ds->k, use_k, partials, stream));
+    PF_DISPATCH(d.n, Ops<NN>::step(shape_of(d), zb, pg, x, x, zb, pg_scale, lam, 0.f, &ds->k, use_k, partials, stream));
   };
 
   hipGraphExec_t gexec = nullptr;
@@ -848,10 +929,10 @@ int pfista_solve(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *ma
     }
     double F = NAN;
     if (prm->eval_objective) {
-      PF_DISPATCH(d.n, Ops<NN>::resid(d, F2(sens), mask, x, F2(b), std::sqrt(inv_l), 1.0 / bnorm,
+      PF_DISPATCH(d.n, Ops<NN>::resid(shape_of(d), F2(sens), mask, x, F2(b), std::sqrt(inv_l), 1.0 / bnorm,
                                       at<float2>(ws, L.t), partials, stream));
       int cnt = 0;
-      PF_DISPATCH(d.n, cnt = Ops<NN>::resid_blocks(d));
+      PF_DISPATCH(d.n, cnt = Ops<NN>::resid_blocks(shape_of(d)));
       reduce(partials, cnt, 1, ds->data, nullptr, stream);
     }
     hipError_t me = hipMemcpyAsync(h, ds->red, 4 * sizeof(double), hipMemcpyDeviceToHost, stream);
@@ -880,6 +961,554 @@ int pfista_solve(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *ma
     if (prm->f_stop > 0 && prm->eval_objective && F <= prm->f_stop) break;
   }
   if (gexec) (void)hipGraphExecDestroy(gexec);
+  r.iters = done;
+  r.status = status;
+  r.normal_applies = (long long)done * (deg + 1);
+  if (rep) *rep = r;
+  return status;
+}
+
+}  // extern "C"
+
+// ============================================================================ batches
+// Slices of uneven shape, grouped by (image side, Haar levels).  A group's
+// buffers are coil-image-major like a plan's, with per-slice coil counts
+// described by the cb / cs tables of Shape.
+struct BGroup {
+  int n = 0, levels = 0;
+  std::vector<int> idx;  // caller's slice indices, in group order
+  std::vector<int> cb;   // first coil image of every slice, then the total
+  std::vector<int> cs;   // slice (in group order) of every coil image
+  int images = 0, cmin = 0, cmax = 0;
+  int seg0 = 0;          // the group's first entry in the batch's per-slice sums
+  size_t o_sens = 0, o_b = 0, o_t = 0, o_mask = 0, o_img[5] = {0, 0, 0, 0, 0}, o_part = 0, o_state = 0;
+  size_t o_cb = 0, o_cs = 0, o_lam = 0;
+  int slices() const { return (int)idx.size(); }
+  size_t n_img() const { return idx.size() * (size_t)n * n; }
+  size_t n_coil() const { return (size_t)images * n * n; }
+};
+
+struct pfista_batch {
+  std::vector<pfista_slice_desc> sl;
+  std::vector<BGroup> g;
+  size_t o_norm = 0, o_npart = 0, o_seg_step = 0, o_seg_data = 0, o_scratch = 0, total = 0;
+  int device = 0;
+  std::string arch;
+};
+
+namespace {
+
+// the launch shape of tuning candidate `cand` for a group
+Shape group_shape(const BGroup &G, void *ws, int cand) {
+  return Shape{G.slices(), G.cmax, G.images, G.levels, PFISTA_MASK_2D, at<int>(ws, G.o_cb), at<int>(ws, G.o_cs),
+               G.cmin, 1 << (cand / 4), (cand / 2) % 2 ? 0 : 1};
+}
+
+void group_chain(const BGroup &G, const Shape &sh, int V, void *ws, const Chain &ch, hipStream_t st, int *k_inc) {
+  const float2 *sens = at<float2>(ws, G.o_sens);
+  const uint8_t *mask = at<uint8_t>(ws, G.o_mask);
+  float2 *t = at<float2>(ws, G.o_t);
+  PF_DISPATCH_V(G.n, V, Ops<NN, VV>::chain(sh, sens, mask, ch.x0, ch.m, ch.alpha, ch.beta, ch.w, ch.y, t, st, k_inc));
+}
+
+// ---- tuner cache: per device architecture and group signature; optionally
+// persisted as "key candidate microseconds" lines in $PFISTA_TUNE_CACHE
+std::mutex g_tune_mu;
+std::vector<std::pair<std::string, std::pair<int, double>>> g_tune;
+bool g_tune_read = false;
+
+std::string tune_key(const std::string &arch, const BGroup &G, int deg) {
+  char buf[320];
+  snprintf(buf, sizeof buf, "%s|n%d|L%d|s%d|ci%d|c%d-%d|d%d", arch.c_str(), G.n, G.levels, G.slices(), G.images,
+           G.cmin, G.cmax, deg);
+  return buf;
+}
+
+void tune_read_file() {
+  g_tune_read = true;
+  const char *path = getenv("PFISTA_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE *f = fopen(path, "r");
+  if (!f) return;
+  char key[320];
+  int cand = 0;
+  double us = 0.0;
+  while (fscanf(f, "%319s %d %lf", key, &cand, &us) == 3)
+    if (cand >= 0 && cand < PFISTA_TUNE_CANDIDATES) g_tune.push_back({key, {cand, us}});
+  fclose(f);
+}
+
+bool tune_lookup(const std::string &key, int &cand, double &us) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (!g_tune_read) tune_read_file();
+  for (auto it = g_tune.rbegin(); it != g_tune.rend(); ++it)
+    if (it->first == key) {
+      cand = it->second.first;
+      us = it->second.second;
+      return true;
+    }
+  return false;
+}
+
+void tune_store(const std::string &key, int cand, double us) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.push_back({key, {cand, us}});
+  const char *path = getenv("PFISTA_TUNE_CACHE");
+  if (!path || !*path) return;
+  if (FILE *f = fopen(path, "a")) {
+    fprintf(f, "%s %d %.3f\n", key.c_str(), cand, us);
+    fclose(f);
+  }
+}
+
+// Time one gradient + polynomial chain of the group for every distinct
+// candidate shape (one warm-up, then three timed chains) and return the fastest.
+int tune_group(const BGroup &G, void *ws, const std::vector<double> &c, hipStream_t st, int &best, double &best_us) {
+  float2 *ahb = at<float2>(ws, G.o_img[0]), *g = at<float2>(ws, G.o_img[1]), *pg = at<float2>(ws, G.o_img[2]);
+  const Chain ch = make_chain(1.0, c, ahb, ahb, g, pg);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  PF_HIP(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(PFISTA_EHIP, "tuner: event create failed");
+  }
+  best = 0;
+  best_us = 0.0;
+  int rc = PFISTA_OK;
+  std::vector<int> seen;
+  for (int k = 0; k < PFISTA_TUNE_CANDIDATES && rc == PFISTA_OK; ++k) {
+    const Shape sh = group_shape(G, ws, k);
+    const int V = k % 2;
+    int rpw = 0;
+    PF_DISPATCH_V(G.n, V, rpw = Ops<NN, VV>::rows_per_block(sh));
+    const int sig = (V * 2 + sh.fused) * 1024 + rpw;
+    if (std::find(seen.begin(), seen.end(), sig) != seen.end()) continue;
+    seen.push_back(sig);
+    group_chain(G, sh, V, ws, ch, st, nullptr);
+    hipError_t he = hipEventRecord(e0, st);
+    for (int r = 0; r < 3 && he == hipSuccess; ++r) group_chain(G, sh, V, ws, ch, st, nullptr);
+    if (he == hipSuccess) he = hipEventRecord(e1, st);
+    if (he == hipSuccess) he = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    if (he != hipSuccess) {
+      rc = fail(PFISTA_EHIP, "tuner: %s", hipGetErrorString(he));
+      break;
+    }
+    rc = launch_status("tuner");
+    const double us = 1e3 * ms / 3.0;
+    if (seen.size() == 1 || us < best_us) {
+      best = k;
+      best_us = us;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
+}
+
+int check_batch_params(const pfista_batch_params *prm, std::vector<double> &c) {
+  if (!prm) return fail(PFISTA_EINVAL, "params is NULL");
+  if (prm->max_iter < 0) return fail(PFISTA_EINVAL, "max_iter < 0");
+  if (prm->check_every < 1 || prm->check_every > 4096) return fail(PFISTA_EINVAL, "check_every outside 1..4096");
+  if (prm->tune < -1 || prm->tune > PFISTA_TUNE_CANDIDATES)
+    return fail(PFISTA_EINVAL, "tune outside -1..%d", PFISTA_TUNE_CANDIDATES);
+  if (prm->streams < 1 || prm->streams > 64) return fail(PFISTA_EINVAL, "streams outside 1..64");
+  if (prm->graph_iters < 0) return fail(PFISTA_EINVAL, "graph_iters < 0");
+  if (prm->coef) {
+    if (prm->degree < 0 || prm->degree > kMaxDegree) return fail(PFISTA_UNSUPPORTED, "degree %d", prm->degree);
+    c.assign(prm->coef, prm->coef + prm->degree + 1);
+    return PFISTA_OK;
+  }
+  return l2_coefficients(prm->degree, c);
+}
+
+// Streams, events and graph of one batch solve, released on every exit path.
+struct BatchRun {
+  std::vector<hipStream_t> br;
+  std::vector<hipEvent_t> join;
+  hipEvent_t fork = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  ~BatchRun() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    for (size_t i = 1; i < br.size(); ++i)
+      if (br[i]) (void)hipStreamDestroy(br[i]);
+    for (hipEvent_t e : join)
+      if (e) (void)hipEventDestroy(e);
+    if (fork) (void)hipEventDestroy(fork);
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+int pfista_batch_create(pfista_batch **out, const pfista_slice_desc *slices, int count) {
+  if (!out) return fail(PFISTA_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (count < 0) return fail(PFISTA_EINVAL, "count < 0");
+  if (count > 0 && !slices) return fail(PFISTA_EINVAL, "slices is NULL");
+  for (int s = 0; s < count; ++s) {
+    const pfista_slice_desc &d = slices[s];
+    if (!supported_n(d.n)) return fail(PFISTA_UNSUPPORTED, "slice %d: image side %d not supported", s, d.n);
+    if (d.coils < 1) return fail(PFISTA_EINVAL, "slice %d: coils must be >= 1", s);
+    if (d.haar_levels < 1 || d.haar_levels > 4)
+      return fail(PFISTA_UNSUPPORTED, "slice %d: haar_levels %d outside 1..4", s, d.haar_levels);
+  }
+  PF_TRY(ensure_twiddles());
+  pfista_batch *b = new (std::nothrow) pfista_batch;
+  if (!b) return fail(PFISTA_EINVAL, "out of host memory");
+  b->sl.assign(slices, slices + count);
+  if (hipGetDevice(&b->device) != hipSuccess) {
+    delete b;
+    return fail(PFISTA_EHIP, "hipGetDevice failed");
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, b->device) == hipSuccess) {
+    b->arch = prop.gcnArchName;
+    const size_t colon = b->arch.find(':');
+    if (colon != std::string::npos) b->arch.resize(colon);
+  } else {
+    b->arch = "unknown";
+  }
+  // groups in ascending (n, levels), slices in caller order inside a group
+  std::vector<int> order(count);
+  for (int s = 0; s < count; ++s) order[s] = s;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+    return slices[a].n != slices[c].n ? slices[a].n < slices[c].n : slices[a].haar_levels < slices[c].haar_levels;
+  });
+  for (int s : order) {
+    const pfista_slice_desc &d = slices[s];
+    if (b->g.empty() || b->g.back().n != d.n || b->g.back().levels != d.haar_levels) {
+      BGroup G;
+      G.n = d.n;
+      G.levels = d.haar_levels;
+      G.cb.push_back(0);
+      G.cmin = d.coils;
+      G.cmax = d.coils;
+      b->g.push_back(G);
+    }
+    BGroup &G = b->g.back();
+    for (int c = 0; c < d.coils; ++c) G.cs.push_back(G.slices());
+    G.idx.push_back(s);
+    G.images += d.coils;
+    G.cb.push_back(G.images);
+    G.cmin = std::min(G.cmin, d.coils);
+    G.cmax = std::max(G.cmax, d.coils);
+  }
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + std::max<size_t>(bytes, 1));
+    return o;
+  };
+  int seg = 0;
+  size_t scratch = 16;
+  for (BGroup &G : b->g) {
+    if (G.images > 65535) {
+      delete b;
+      return fail(PFISTA_UNSUPPORTED, "group of side %d holds %d coil images (> 65535)", G.n, G.images);
+    }
+    G.seg0 = seg;
+    seg += G.slices();
+    G.o_sens = take(G.n_coil() * sizeof(float2));
+    G.o_b = take(G.n_coil() * sizeof(float2));
+    G.o_t = take(G.n_coil() * sizeof(float2));
+    G.o_mask = take(G.n_img());
+    for (int i = 0; i < 5; ++i) G.o_img[i] = take(G.n_img() * sizeof(float2));
+    int rpi = 0;
+    for (int v = 0; v < pf::kVariants; ++v) {
+      int r = 0;
+      PF_DISPATCH_V(G.n, v, r = Ops<NN, VV>::resid_per_image());
+      rpi = std::max(rpi, r);
+    }
+    const size_t n_part = std::max<size_t>({(size_t)3 * G.slices() * (G.n / 16) * (G.n / 16),
+                                            (size_t)rpi * G.images, (size_t)16});
+    G.o_part = take(n_part * sizeof(double));
+    G.o_state = take(sizeof(DevState));
+    G.o_cb = take(G.cb.size() * sizeof(int));
+    G.o_cs = take(G.cs.size() * sizeof(int));
+    G.o_lam = take(G.idx.size() * sizeof(float));
+    for (int s : G.idx) {
+      const pfista_desc d1{G.n, slices[s].coils, 1, G.levels, PFISTA_MASK_2D};
+      scratch = std::max(scratch, layout(d1).total);
+    }
+  }
+  b->o_norm = take((size_t)count * sizeof(double));
+  b->o_npart = take((size_t)kNormBlocks * sizeof(double));
+  b->o_seg_step = take((size_t)count * 3 * sizeof(double));
+  b->o_seg_data = take((size_t)count * sizeof(double));
+  b->o_scratch = take(scratch);
+  b->total = off;
+  *out = b;
+  return PFISTA_OK;
+}
+
+void pfista_batch_destroy(pfista_batch *b) { delete b; }
+
+size_t pfista_batch_workspace_bytes(const pfista_batch *b) { return b ? b->total : 0; }
+
+int pfista_batch_groups(const pfista_batch *b) { return b ? (int)b->g.size() : 0; }
+
+int pfista_batch_solve(const pfista_batch *b, const pfista_c32 *const *sens, const uint8_t *const *mask,
+                       const pfista_c32 *const *kspace, const double *lambda, const double *inv_l,
+                       const pfista_batch_params *prm, pfista_c32 *const *x_out, pfista_slice_report *slice_rep,
+                       pfista_group_report *group_rep, pfista_batch_report *rep, void *ws, hipStream_t stream) {
+  if (!b) return fail(PFISTA_EINVAL, "batch is NULL");
+  std::vector<double> c;
+  PF_TRY(check_batch_params(prm, c));
+  const int count = (int)b->sl.size();
+  pfista_batch_report r{};
+  r.status = PFISTA_OK;
+  if (count == 0) {
+    if (rep) *rep = r;
+    return PFISTA_OK;
+  }
+  if (!sens || !mask || !kspace || !lambda || !x_out) return fail(PFISTA_EINVAL, "a per-slice pointer array is NULL");
+  PF_TRY(check_ptr(ws, "ws", 16));
+  bool need_power = false;
+  for (int s = 0; s < count; ++s) {
+    char nm[64];
+    snprintf(nm, sizeof nm, "sens[%d]", s);
+    PF_TRY(check_ptr(sens[s], nm));
+    snprintf(nm, sizeof nm, "mask[%d]", s);
+    PF_TRY(check_ptr(mask[s], nm, 1));
+    snprintf(nm, sizeof nm, "kspace[%d]", s);
+    PF_TRY(check_ptr(kspace[s], nm));
+    snprintf(nm, sizeof nm, "x_out[%d]", s);
+    PF_TRY(check_ptr(x_out[s], nm));
+    if (!(lambda[s] >= 0.0) || !std::isfinite(lambda[s])) return fail(PFISTA_EINVAL, "lambda[%d] must be finite and >= 0", s);
+    const double il = inv_l ? inv_l[s] : 0.0;
+    if (!(il >= 0.0) || !std::isfinite(il)) return fail(PFISTA_EINVAL, "inv_l[%d] must be finite and >= 0", s);
+    need_power = need_power || il == 0.0;
+  }
+  if (need_power && prm->power_iters < 1) return fail(PFISTA_EINVAL, "estimating inv_l needs power_iters >= 1");
+  int dev = 0;
+  PF_HIP(hipGetDevice(&dev));
+  if (dev != b->device) return fail(PFISTA_EINVAL, "batch was created on device %d, current is %d", b->device, dev);
+  const int deg = (int)c.size() - 1;
+  const int ng = (int)b->g.size();
+
+  // ---- setup: ||b_s||, L_s, normalised copies, A'^H b'
+  double *norm = at<double>(ws, b->o_norm);
+  double *npart = at<double>(ws, b->o_npart);
+  for (int s = 0; s < count; ++s)
+    norm2_dev(F2(kspace[s]), (size_t)b->sl[s].coils * b->sl[s].n * b->sl[s].n, npart, norm + s, stream);
+  PF_TRY(launch_status("pfista_batch_solve(norm)"));
+  std::vector<double> il(count), bn(count);
+  for (int s = 0; s < count; ++s) {
+    il[s] = inv_l ? inv_l[s] : 0.0;
+    if (il[s] == 0.0) {
+      const pfista_slice_desc &d = b->sl[s];
+      pfista_plan tmp;
+      tmp.d = pfista_desc{d.n, d.coils, 1, d.haar_levels, PFISTA_MASK_2D};
+      tmp.device = dev;
+      double lam = 0.0;
+      PF_TRY(pfista_power_iteration(&tmp, sens[s], mask[s], nullptr, prm->power_iters, &lam,
+                                    at<void>(ws, b->o_scratch), stream));
+      if (!(lam > 0.0)) return fail(PFISTA_EINVAL, "slice %d: power iteration gave %g", s, lam);
+      il[s] = 1.0 / (1.01 * lam);
+    }
+  }
+  PF_HIP(hipMemcpyAsync(bn.data(), norm, count * sizeof(double), hipMemcpyDeviceToHost, stream));
+  PF_HIP(hipStreamSynchronize(stream));
+  for (int s = 0; s < count; ++s) bn[s] = std::sqrt(bn[s]);
+
+  std::vector<std::vector<float>> lam_h(ng);
+  const int k_init = -1;   // the first gradient apply advances it to 0
+  for (int gi = 0; gi < ng; ++gi) {
+    const BGroup &G = b->g[gi];
+    const size_t nn = (size_t)G.n * G.n;
+    for (int s : G.idx) lam_h[gi].push_back((float)lambda[s]);
+    PF_HIP(hipMemcpyAsync(at<int>(ws, G.o_cb), G.cb.data(), G.cb.size() * sizeof(int), hipMemcpyHostToDevice, stream));
+    PF_HIP(hipMemcpyAsync(at<int>(ws, G.o_cs), G.cs.data(), G.cs.size() * sizeof(int), hipMemcpyHostToDevice, stream));
+    PF_HIP(hipMemcpyAsync(at<float>(ws, G.o_lam), lam_h[gi].data(), lam_h[gi].size() * sizeof(float),
+                          hipMemcpyHostToDevice, stream));
+    float2 *sg = at<float2>(ws, G.o_sens), *bg = at<float2>(ws, G.o_b);
+    uint8_t *mg = at<uint8_t>(ws, G.o_mask);
+    for (int j = 0; j < G.slices(); ++j) {
+      const int s = G.idx[j];
+      const size_t nc = (size_t)b->sl[s].coils * nn;
+      pf::k_scale<<<blocks_for(nc), 256, 0, stream>>>(F2(sens[s]), sg + (size_t)G.cb[j] * nn, nc,
+                                                      (float)std::sqrt(il[s]));
+      pf::k_scale<<<blocks_for(nc), 256, 0, stream>>>(F2(kspace[s]), bg + (size_t)G.cb[j] * nn, nc,
+                                                      bn[s] > 0.0 ? (float)(1.0 / bn[s]) : 0.f);
+      PF_HIP(hipMemcpyAsync(mg + (size_t)j * nn, mask[s], nn, hipMemcpyDeviceToDevice, stream));
+    }
+    const Shape sh0 = group_shape(G, ws, 0);
+    PF_DISPATCH_V(G.n, 0, Ops<NN, VV>::adjoint(sh0, sg, mg, bg, at<float2>(ws, G.o_img[0]), 1.f,
+                                               at<float2>(ws, G.o_t), stream));
+    pf::k_fill<<<blocks_for(G.n_img()), 256, 0, stream>>>(at<float2>(ws, G.o_img[3]), G.n_img(), make_float2(0.f, 0.f));
+    pf::k_fill<<<blocks_for(G.n_img()), 256, 0, stream>>>(at<float2>(ws, G.o_img[4]), G.n_img(), make_float2(0.f, 0.f));
+    PF_HIP(hipMemcpyAsync(&at<DevState>(ws, G.o_state)->k, &k_init, sizeof(int), hipMemcpyHostToDevice, stream));
+  }
+  PF_TRY(launch_status("pfista_batch_solve(setup)"));
+
+  // ---- launch shape per group
+  std::vector<int> cand(ng, 0);
+  std::vector<double> cand_us(ng, 0.0);
+  for (int gi = 0; gi < ng; ++gi) {
+    if (prm->tune >= 1) {
+      cand[gi] = prm->tune - 1;
+    } else if (prm->tune == -1) {
+      const std::string key = tune_key(b->arch, b->g[gi], deg);
+      if (!tune_lookup(key, cand[gi], cand_us[gi])) {
+        PF_TRY(tune_group(b->g[gi], ws, c, stream, cand[gi], cand_us[gi]));
+        tune_store(key, cand[gi], cand_us[gi]);
+      }
+    }
+  }
+  std::vector<Shape> shp(ng);
+  for (int gi = 0; gi < ng; ++gi) shp[gi] = group_shape(b->g[gi], ws, cand[gi]);
+
+  // ---- branches: groups spread by longest-processing-time on coil-image pixels
+  BatchRun run;
+  const int nb = std::min(prm->streams, ng);
+  run.br.assign(nb, stream);
+  std::vector<int> branch(ng, 0);
+  if (nb > 1) {
+    for (int i = 1; i < nb; ++i) PF_HIP(hipStreamCreateWithFlags(&run.br[i], hipStreamNonBlocking));
+    PF_HIP(hipEventCreateWithFlags(&run.fork, hipEventDisableTiming));
+    run.join.assign(nb, nullptr);
+    for (int i = 1; i < nb; ++i) PF_HIP(hipEventCreateWithFlags(&run.join[i], hipEventDisableTiming));
+    std::vector<int> ord(ng);
+    for (int gi = 0; gi < ng; ++gi) ord[gi] = gi;
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int q) { return b->g[a].n_coil() > b->g[q].n_coil(); });
+    std::vector<double> load(nb, 0.0);
+    for (int gi : ord) {
+      const int tgt = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      branch[gi] = tgt;
+      load[tgt] += (double)b->g[gi].n_coil();
+    }
+  }
+
+  const int use_k = prm->momentum ? 1 : 0;
+  auto body = [&]() -> hipError_t {
+    hipError_t he = hipSuccess;
+    if (nb > 1) {
+      he = hipEventRecord(run.fork, stream);
+      for (int i = 1; i < nb && he == hipSuccess; ++i) he = hipStreamWaitEvent(run.br[i], run.fork, 0);
+      if (he != hipSuccess) return he;
+    }
+    for (int gi = 0; gi < ng; ++gi) {
+      const BGroup &G = b->g[gi];
+      hipStream_t st = run.br[branch[gi]];
+      float2 *ahb = at<float2>(ws, G.o_img[0]), *g = at<float2>(ws, G.o_img[1]), *pg = at<float2>(ws, G.o_img[2]);
+      float2 *x = at<float2>(ws, G.o_img[3]), *z = at<float2>(ws, G.o_img[4]);
+      DevState *ds = at<DevState>(ws, G.o_state);
+      const Chain ch = make_chain(1.0, c, z, ahb, g, pg);
+      const int V = cand[gi] % 2;
+      group_chain(G, shp[gi], V, ws, ch, st, &ds->k);
+      const float2 *pgp = deg == 0 ? g : pg;
+      const float pg_scale = deg == 0 ? (float)c[0] : 1.f;
+      PF_DISPATCH_V(G.n, V, Ops<NN, VV>::step(shp[gi], z, pgp, x, x, z, pg_scale, 0.f, 0.f, &ds->k, use_k,
+                                              at<double>(ws, G.o_part), st, at<float>(ws, G.o_lam)));
+    }
+    if (nb > 1) {
+      for (int i = 1; i < nb && he == hipSuccess; ++i) he = hipEventRecord(run.join[i], run.br[i]);
+      for (int i = 1; i < nb && he == hipSuccess; ++i) he = hipStreamWaitEvent(stream, run.join[i], 0);
+    }
+    return he;
+  };
+
+  int gunroll = 0;
+  if (prm->graph_iters > 0 && stream != nullptr && prm->max_iter > 0) {
+    gunroll = std::min(prm->graph_iters, prm->check_every);
+    hipGraph_t graph = nullptr;
+    PF_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+    hipError_t be = hipSuccess;
+    for (int i = 0; i < gunroll && be == hipSuccess; ++i) be = body();
+    hipError_t ce = hipStreamEndCapture(stream, &graph);
+    if (be != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return fail(PFISTA_EHIP, "graph capture: %s", hipGetErrorString(be));
+    }
+    if (ce != hipSuccess) return fail(PFISTA_EHIP, "graph capture: %s", hipGetErrorString(ce));
+    hipError_t ie = hipGraphInstantiate(&run.gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) return fail(PFISTA_EHIP, "graph instantiate: %s", hipGetErrorString(ie));
+  }
+
+  double *seg_step = at<double>(ws, b->o_seg_step), *seg_data = at<double>(ws, b->o_seg_data);
+  std::vector<double> hs((size_t)count * 3), hd(count, 0.0);
+  std::vector<pfista_slice_report> sr(count);
+  for (int s = 0; s < count; ++s) {
+    sr[s] = pfista_slice_report{NAN, 0.0, 0.0, il[s], bn[s]};
+  }
+  int done = 0, status = PFISTA_OK;
+  while (done < prm->max_iter) {
+    const int chunk = std::min(prm->check_every, prm->max_iter - done);
+    int left = chunk;
+    if (run.gexec) {
+      while (left >= gunroll) {
+        hipError_t le = hipGraphLaunch(run.gexec, stream);
+        if (le != hipSuccess) return fail(PFISTA_EHIP, "graph launch: %s", hipGetErrorString(le));
+        left -= gunroll;
+      }
+    }
+    for (; left > 0; --left) {
+      hipError_t be = body();
+      if (be != hipSuccess) return fail(PFISTA_EHIP, "pfista_batch_solve(loop): %s", hipGetErrorString(be));
+    }
+    done += chunk;
+    // per-slice FP64 sums of the chunk's last step, and optionally the data term
+    for (int gi = 0; gi < ng; ++gi) {
+      const BGroup &G = b->g[gi];
+      double *part = at<double>(ws, G.o_part);
+      pf::k_reduce_seg<<<G.slices(), 64, 0, stream>>>(part, nullptr, (G.n / 16) * (G.n / 16), 3,
+                                                      seg_step + 3 * (size_t)G.seg0);
+      if (prm->eval_objective) {
+        const int V = cand[gi] % 2;
+        int rpi = 0;
+        PF_DISPATCH_V(G.n, V, rpi = Ops<NN, VV>::resid_per_image());
+        PF_DISPATCH_V(G.n, V, Ops<NN, VV>::resid(shp[gi], at<float2>(ws, G.o_sens), at<uint8_t>(ws, G.o_mask),
+                                                 at<float2>(ws, G.o_img[3]), at<float2>(ws, G.o_b), 1.0, 1.0,
+                                                 at<float2>(ws, G.o_t), part, stream));
+        pf::k_reduce_seg<<<G.slices(), 64, 0, stream>>>(part, at<int>(ws, G.o_cb), rpi, 1, seg_data + G.seg0);
+      }
+    }
+    PF_TRY(launch_status("pfista_batch_solve(check)"));
+    PF_HIP(hipMemcpyAsync(hs.data(), seg_step, hs.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
+    if (prm->eval_objective)
+      PF_HIP(hipMemcpyAsync(hd.data(), seg_data, hd.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
+    PF_HIP(hipStreamSynchronize(stream));
+    bool all_tol = prm->tol > 0;
+    bool bad = false;
+    for (const BGroup &G : b->g)
+      for (int j = 0; j < G.slices(); ++j) {
+        const int s = G.idx[j];
+        const size_t q = (size_t)G.seg0 + j;
+        const double l1 = hs[3 * q], dx2 = hs[3 * q + 1], xn2 = hs[3 * q + 2];
+        sr[s].l1 = l1;
+        sr[s].rel_change = xn2 > 0 ? std::sqrt(dx2 / xn2) : 0.0;
+        if (prm->eval_objective) sr[s].objective = 0.5 * hd[q] + lambda[s] * l1;
+        bad = bad || !std::isfinite(l1) || !std::isfinite(dx2) || !std::isfinite(xn2) ||
+              (prm->eval_objective && (!std::isfinite(sr[s].objective) || sr[s].objective > 5.0));
+        all_tol = all_tol && sr[s].rel_change <= prm->tol;
+      }
+    if (bad) {
+      status = PFISTA_DIVERGED;
+      fail(PFISTA_DIVERGED, "a slice diverged after %d iterations", done);
+      break;
+    }
+    if (all_tol) break;
+  }
+
+  // ---- outputs
+  for (const BGroup &G : b->g) {
+    const size_t nn = (size_t)G.n * G.n;
+    for (int j = 0; j < G.slices(); ++j)
+      PF_HIP(hipMemcpyAsync(x_out[G.idx[j]], at<float2>(ws, G.o_img[3]) + (size_t)j * nn, nn * sizeof(float2),
+                            hipMemcpyDeviceToDevice, stream));
+  }
+  PF_HIP(hipStreamSynchronize(stream));
+  if (slice_rep)
+    for (int s = 0; s < count; ++s) slice_rep[s] = sr[s];
+  if (group_rep)
+    for (int gi = 0; gi < ng; ++gi) {
+      const BGroup &G = b->g[gi];
+      group_rep[gi] = pfista_group_report{G.n, G.levels, G.slices(), G.images, cand[gi], cand_us[gi]};
+    }
   r.iters = done;
   r.status = status;
   r.normal_applies = (long long)done * (deg + 1);

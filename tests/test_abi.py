@@ -81,3 +81,24 @@ def test_host_coefficient_argument_errors(lib):
     for bad in ((2, 0.0), (2, 1.0), (9, 0.5)):
         with pytest.raises(pf.PfistaError):
             pf.poly_coefficients_chebyshev(*bad)
+
+
+@pytest.mark.parametrize("sl,code", [
+    ((100, 4, 3), -2), ((64, 0, 3), -1), ((64, 4, 0), -2), ((64, 4, 5), -2),
+])
+def test_batch_validation_before_any_gpu_call(lib, sl, code):
+    import paper_2204_10252_amd as pf
+    arr = (pf._SliceDesc * 2)(pf._SliceDesc(64, 4, 3), pf._SliceDesc(*sl))
+    h = ctypes.c_void_p()
+    assert lib.pfista_batch_create(ctypes.byref(h), arr, 2) == code
+    assert lib.pfista_last_error().decode()
+    assert lib.pfista_batch_create(ctypes.byref(h), arr, -1) == -1
+
+
+def test_null_batch_is_rejected(lib):
+    import paper_2204_10252_amd as pf
+    prm = pf._BatchParams(3, None, 10, 10, 0.0, 0, 30, 0, 1, 1, 0)
+    rc = lib.pfista_batch_solve(None, None, None, None, None, None, ctypes.byref(prm), None, None, None,
+                                None, None, None)
+    assert rc == -1 and b"batch" in lib.pfista_last_error()
+    assert lib.pfista_batch_workspace_bytes(None) == 0 and lib.pfista_batch_groups(None) == 0
