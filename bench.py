@@ -17,6 +17,9 @@ iterations (inputs resident in HBM, graph-replayed loop).  Also reported:
   relative iterate error, each method against its own converged solution;
 * the slab workload (32 slices 384 x 384, 32 coils, phase-encode mask): the
   HBM-streaming normal operator and a degree-4 PFISTA iteration;
+* the batch workload (64 uneven slices): the batched solver's loop time with
+  tuned and default launch shapes, 1 and 4 concurrent branches, against
+  solving the slices one plan at a time;
 * the FP64 oracle timed on the host cores on a bounded sample (cpu_baseline).
 
 Prints one JSON line on stdout; progress goes to stderr.
@@ -236,6 +239,85 @@ def slab_benchmark(torch, pf, dev, stream, reps=20, iters=30, graph_iters=10):
             "pfista_d4_ms_per_iteration": round(1e3 * dt / iters, 4)}
 
 
+def batch_benchmark(torch, pf, dev, stream, graph_iters=10, k_short=10, k_long=60, reps=2):
+    """Workload 4: 64 uneven slices (N in {128..320}, C in {8, 12, 16, 32},
+    per-slice R and lambda), degree 3.  Loop time per iteration from the
+    difference of a long and a short solve (setup cancels)."""
+    import numpy as np
+
+    from synth import make_slice_inputs
+    slices = [make_slice_inputs(4, s) for s in range(64)]
+    sens, mask, b, lam, shapes = [], [], [], [], []
+    for sl in slices:
+        n, C = sl["n"], sl["coils"]
+        plan = pf.Plan(n, C, 1, haar_levels=sl["levels"], device=dev)
+        st = torch.from_numpy(sl["sens"].astype(np.complex64)).to(dev)
+        mk = torch.from_numpy(sl["mask"]).to(dev)
+        im = torch.from_numpy(sl["phantom"].astype(np.complex64)).to(dev)
+        bb = torch.empty((C, n, n), dtype=torch.complex64, device=dev)
+        pf.forward(plan, st, mk, im, bb)                                      # M F S x on the GPU
+        bb += torch.from_numpy(sl["noise"].astype(np.complex64)).to(dev) * mk.to(torch.complex64)
+        sens.append(st), mask.append(mk), b.append(bb), lam.append(sl["lam"])
+        shapes.append((n, C, sl["levels"]))
+    batch = pf.Batch(shapes, device=dev)
+    xs = [torch.empty((n, n), dtype=torch.complex64, device=dev) for n, _, _ in shapes]
+    coef = pf.poly_coefficients(3)
+    with torch.cuda.stream(stream):
+        rep = pf.batch_solve(batch, sens, mask, b, xs, lam, coef=coef, max_iter=0, inv_l=None, power_iters=30,
+                             stream=stream)
+    inv_l = [r["inv_l"] for r in rep["slices"]]
+
+    def run(iters, **kw):
+        with torch.cuda.stream(stream):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = pf.batch_solve(batch, sens, mask, b, xs, lam, coef=coef, max_iter=iters, inv_l=inv_l,
+                               check_every=iters, graph_iters=graph_iters, stream=stream, **kw)
+            torch.cuda.synchronize()
+        return time.perf_counter() - t0, r
+
+    def per_iteration(**kw):
+        run(k_short, **kw)                                    # tunes (first time) and warms up
+        ts = min(run(k_short, **kw)[0] for _ in range(reps))
+        tl, r = min((run(k_long, **kw) for _ in range(reps)), key=lambda v: v[0])
+        return (tl - ts) / (k_long - k_short), r
+
+    sweep_bytes = sum(8 * n * n * (C + 2) + n * n for n, C, _ in shapes)
+    out = {"workload": "64 uneven slices, N in {128,160,192,256,320}, C in {8,12,16,32}, "
+                       "2-D variable-density masks R ~ U[3,8], per-slice lambda, 4-level Haar",
+           "degree": 3, "algorithmic_bytes_per_apply_sweep": sweep_bytes, "configs": {}}
+    for name, kw in (("tuned_4_branches", dict(tune=-1, streams=4)), ("tuned_1_branch", dict(tune=-1, streams=1)),
+                     ("default_1_branch", dict(tune=0, streams=1))):
+        t, r = per_iteration(**kw)
+        out["configs"][name] = {"ms_per_iteration": round(1e3 * t, 4),
+                                "apply_sweeps_per_s": round(4 / t, 1),
+                                "slice_applies_per_s": round(64 * 4 / t, 1),
+                                "hbm_gbs_algorithmic": round(4 * sweep_bytes / t / 1e9, 1),
+                                "hbm_frac": round(4 * sweep_bytes / t / 1e9 / PEAK_HBM_GBS, 4),
+                                "groups": [{k: g[k] for k in ("n", "slices", "coil_images", "candidate", "chain_us")}
+                                           for g in r["groups"]]}
+        log(f"batch {name}: {out['configs'][name]['ms_per_iteration']} ms/iteration")
+    # the same slices solved one plan at a time with the single-slice solver
+    plans = [pf.Plan(n, C, 1, haar_levels=L, device=dev) for n, C, L in shapes]
+
+    def loop(iters):
+        with torch.cuda.stream(stream):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i, pl in enumerate(plans):
+                pf.solve(pl, sens[i], mask[i], b[i], xs[i], lam[i], coef=coef, max_iter=iters, inv_l=inv_l[i],
+                         check_every=iters, graph_iters=graph_iters, stream=stream)
+            torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    loop(k_short)
+    t = (min(loop(k_long) for _ in range(reps)) - min(loop(k_short) for _ in range(reps))) / (k_long - k_short)
+    out["looped_single_slice"] = {"ms_per_iteration": round(1e3 * t, 4), "apply_sweeps_per_s": round(4 / t, 1)}
+    best = min(v["ms_per_iteration"] for v in out["configs"].values())
+    out["speedup_vs_looped"] = round(1e3 * t / best, 3)
+    return out
+
+
 def cpu_baseline(inp, degree, seconds):
     """The FP64 oracle's PFISTA iterations on the host, for a bounded time."""
     import numpy as np
@@ -270,6 +352,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-tolerance comparison")
     ap.add_argument("--no-slab", action="store_true", help="skip the 32-slice slab workload")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-slice uneven batch workload")
     ap.add_argument("--profile-only", action="store_true",
                     help="only the per-pass kernel timing (for a matching rocprofv3 kernel-trace run)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -356,6 +439,13 @@ def main():
         slab = slab_benchmark(torch, pf, dev, stream, graph_iters=args.graph_iters)
         log(f"slab: {slab}")
 
+    batch = None
+    if not args.no_batch:
+        log("uneven batch workload")
+        torch.cuda.empty_cache()
+        batch = batch_benchmark(torch, pf, dev, stream, graph_iters=args.graph_iters)
+        log(f"batch: {batch['configs']}, looped single-slice {batch['looped_single_slice']}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"cpu baseline ({args.cpu_seconds:.0f} s)")
@@ -381,6 +471,7 @@ def main():
         "cpu_baseline": cpu,
         "time_to_tol": ttt,
         "slab": slab,
+        "batch": batch,
     }
     print(json.dumps(out), flush=True)
 
