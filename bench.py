@@ -259,7 +259,8 @@ def batch_benchmark(torch, pf, dev, stream, graph_iters=10, k_short=10, k_long=6
         bb += torch.from_numpy(sl["noise"].astype(np.complex64)).to(dev) * mk.to(torch.complex64)
         sens.append(st), mask.append(mk), b.append(bb), lam.append(sl["lam"])
         shapes.append((n, C, sl["levels"]))
-    batch = pf.Batch(shapes, device=dev)
+    batches = {0: pf.Batch(shapes, device=dev)}
+    batch = batches[0]
     xs = [torch.empty((n, n), dtype=torch.complex64, device=dev) for n, _, _ in shapes]
     coef = pf.poly_coefficients(3)
     with torch.cuda.stream(stream):
@@ -267,11 +268,13 @@ def batch_benchmark(torch, pf, dev, stream, graph_iters=10, k_short=10, k_long=6
                              stream=stream)
     inv_l = [r["inv_l"] for r in rep["slices"]]
 
-    def run(iters, **kw):
+    def run(iters, chunk_mb=0, **kw):
+        if chunk_mb not in batches:
+            batches[chunk_mb] = pf.Batch(shapes, chunk_bytes=chunk_mb << 20, device=dev)
         with torch.cuda.stream(stream):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            r = pf.batch_solve(batch, sens, mask, b, xs, lam, coef=coef, max_iter=iters, inv_l=inv_l,
+            r = pf.batch_solve(batches[chunk_mb], sens, mask, b, xs, lam, coef=coef, max_iter=iters, inv_l=inv_l,
                                check_every=iters, graph_iters=graph_iters, stream=stream, **kw)
             torch.cuda.synchronize()
         return time.perf_counter() - t0, r
@@ -286,7 +289,9 @@ def batch_benchmark(torch, pf, dev, stream, graph_iters=10, k_short=10, k_long=6
     out = {"workload": "64 uneven slices, N in {128,160,192,256,320}, C in {8,12,16,32}, "
                        "2-D variable-density masks R ~ U[3,8], per-slice lambda, 4-level Haar",
            "degree": 3, "algorithmic_bytes_per_apply_sweep": sweep_bytes, "configs": {}}
-    for name, kw in (("tuned_4_branches", dict(tune=-1, streams=4)), ("tuned_1_branch", dict(tune=-1, streams=1)),
+    for name, kw in (("tuned_16MB_groups_4_branches", dict(chunk_mb=16, tune=-1, streams=4)),
+                     ("tuned_2_branches", dict(tune=-1, streams=2)),
+                     ("tuned_1_branch", dict(tune=-1, streams=1)),
                      ("default_1_branch", dict(tune=0, streams=1))):
         t, r = per_iteration(**kw)
         out["configs"][name] = {"ms_per_iteration": round(1e3 * t, 4),
@@ -294,7 +299,7 @@ def batch_benchmark(torch, pf, dev, stream, graph_iters=10, k_short=10, k_long=6
                                 "slice_applies_per_s": round(64 * 4 / t, 1),
                                 "hbm_gbs_algorithmic": round(4 * sweep_bytes / t / 1e9, 1),
                                 "hbm_frac": round(4 * sweep_bytes / t / 1e9 / PEAK_HBM_GBS, 4),
-                                "groups": [{k: g[k] for k in ("n", "slices", "coil_images", "candidate", "chain_us")}
+                                "groups": [{k: g[k] for k in ("n", "slices", "coil_images", "candidate")}
                                            for g in r["groups"]]}
         log(f"batch {name}: {out['configs'][name]['ms_per_iteration']} ms/iteration")
     # the same slices solved one plan at a time with the single-slice solver

@@ -241,8 +241,14 @@ typedef struct pfista_batch pfista_batch;
 #define PFISTA_TUNE_CANDIDATES 12
 
 /* Validate and group `count` slices (HOST array); count >= 0, at most 65535
- * coil images per group.  Returns EINVAL / UNSUPPORTED on a bad slice. */
-int pfista_batch_create(pfista_batch **out, const pfista_slice_desc *slices, int count);
+ * coil images per group.  chunk_bytes > 0 caps the coil-map bytes of a group
+ * (a slice larger than the cap forms a group of its own): a group's loop then
+ * keeps its coil maps and transform buffer inside the GPU's last-level cache
+ * (256 MB Infinity Cache on MI355X) across the passes of an iteration;
+ * 0 groups every slice of an image side and level count together.  Returns
+ * EINVAL / UNSUPPORTED on a bad slice. */
+int pfista_batch_create(pfista_batch **out, const pfista_slice_desc *slices, int count,
+                        size_t chunk_bytes);
 void pfista_batch_destroy(pfista_batch *b);
 /* Device workspace for pfista_batch_solve: about three times the coil-map
  * bytes of all slices (normalised copies of maps and data, transform buffer)

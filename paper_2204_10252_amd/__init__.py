@@ -99,7 +99,7 @@ _SIGS = {
                           ctypes.POINTER(_D), ctypes.POINTER(_Report), _VP, _VP]),
     "pfista_profile_normal": (_I, [_VP, _VP, _VP, _VP, _VP, _I, ctypes.POINTER(_F),
                                    ctypes.POINTER(_I), _VP, _VP]),
-    "pfista_batch_create": (_I, [ctypes.POINTER(_VP), ctypes.POINTER(_SliceDesc), _I]),
+    "pfista_batch_create": (_I, [ctypes.POINTER(_VP), ctypes.POINTER(_SliceDesc), _I, ctypes.c_size_t]),
     "pfista_batch_destroy": (None, [_VP]),
     "pfista_batch_workspace_bytes": (ctypes.c_size_t, [_VP]),
     "pfista_batch_groups": (_I, [_VP]),
@@ -363,9 +363,10 @@ def solve(plan, sens, mask, b, x, lam, degree=3, coef=None, max_iter=50, inv_l=0
 
 class Batch:
     """Owns a ``pfista_batch`` (slices of uneven shape) and its device workspace.
-    ``slices``: sequence of ``(n, coils)`` or ``(n, coils, haar_levels)``."""
+    ``slices``: sequence of ``(n, coils)`` or ``(n, coils, haar_levels)``;
+    ``chunk_bytes``: cap on the coil-map bytes of one group (0: no cap)."""
 
-    def __init__(self, slices, haar_levels=4, device=None):
+    def __init__(self, slices, haar_levels=4, chunk_bytes=0, device=None):
         import torch
         lib = load_library()
         sl = [tuple(int(v) for v in t) for t in slices]
@@ -374,7 +375,7 @@ class Batch:
         h = ctypes.c_void_p()
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         with torch.cuda.device(self.device):
-            _check(lib.pfista_batch_create(ctypes.byref(h), arr, len(self.slices)))
+            _check(lib.pfista_batch_create(ctypes.byref(h), arr, len(self.slices), int(chunk_bytes)))
         self._h = h
         self.groups = int(lib.pfista_batch_groups(h))
         nbytes = int(lib.pfista_batch_workspace_bytes(h))

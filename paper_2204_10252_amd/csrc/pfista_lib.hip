@@ -1143,7 +1143,7 @@ struct BatchRun {
 
 extern "C" {
 
-int pfista_batch_create(pfista_batch **out, const pfista_slice_desc *slices, int count) {
+int pfista_batch_create(pfista_batch **out, const pfista_slice_desc *slices, int count, size_t chunk_bytes) {
   if (!out) return fail(PFISTA_EINVAL, "out is NULL");
   *out = nullptr;
   if (count < 0) return fail(PFISTA_EINVAL, "count < 0");
@@ -1179,7 +1179,9 @@ int pfista_batch_create(pfista_batch **out, const pfista_slice_desc *slices, int
   });
   for (int s : order) {
     const pfista_slice_desc &d = slices[s];
-    if (b->g.empty() || b->g.back().n != d.n || b->g.back().levels != d.haar_levels) {
+    const size_t bytes = (size_t)d.coils * d.n * d.n * sizeof(float2);
+    if (b->g.empty() || b->g.back().n != d.n || b->g.back().levels != d.haar_levels ||
+        (chunk_bytes > 0 && b->g.back().n_coil() * sizeof(float2) + bytes > chunk_bytes)) {
       BGroup G;
       G.n = d.n;
       G.levels = d.haar_levels;

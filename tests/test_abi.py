@@ -90,9 +90,9 @@ def test_batch_validation_before_any_gpu_call(lib, sl, code):
     import paper_2204_10252_amd as pf
     arr = (pf._SliceDesc * 2)(pf._SliceDesc(64, 4, 3), pf._SliceDesc(*sl))
     h = ctypes.c_void_p()
-    assert lib.pfista_batch_create(ctypes.byref(h), arr, 2) == code
+    assert lib.pfista_batch_create(ctypes.byref(h), arr, 2, 0) == code
     assert lib.pfista_last_error().decode()
-    assert lib.pfista_batch_create(ctypes.byref(h), arr, -1) == -1
+    assert lib.pfista_batch_create(ctypes.byref(h), arr, -1, 0) == -1
 
 
 def test_null_batch_is_rejected(lib):

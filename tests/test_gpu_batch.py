@@ -45,10 +45,10 @@ def prepare(sl, inv_l="power"):
             "lam": sl["lam"], "levels": sl["levels"], "n": sl["n"], "coils": sl["coils"]}
 
 
-def run_batch(slices, coef, iters, **kw):
+def run_batch(slices, coef, iters, chunk_bytes=0, **kw):
     import torch
     import paper_2204_10252_amd as pf
-    batch = pf.Batch([(p["n"], p["coils"], p["levels"]) for p in slices])
+    batch = pf.Batch([(p["n"], p["coils"], p["levels"]) for p in slices], chunk_bytes=chunk_bytes)
     xs = [torch.empty((p["n"], p["n"]), dtype=torch.complex64, device="cuda") for p in slices]
     inv_l = kw.pop("inv_l", [p["inv_l"] for p in slices])
     rep = pf.batch_solve(batch, [to_dev(p["sens"][0]) for p in slices], [to_dev(p["mask"][0]) for p in slices],
@@ -122,6 +122,16 @@ def test_autotune_streams_and_graph(tiny, tiny_oracle):
     assert [g["candidate"] for g in rep2["groups"]] == [g["candidate"] for g in rep["groups"]]
     assert [g["chain_us"] for g in rep2["groups"]] == [g["chain_us"] for g in rep["groups"]]
     for x, (xo, _, _) in zip(xs2, ref):
+        assert rel(x[None], xo) <= 1e-4
+
+
+def test_chunked_groups(tiny, tiny_oracle):
+    # a cap of 5 coil images of 64 x 64 splits the (64, L3) group (4 + 2 + 6 coils) in three
+    coef, ref = tiny_oracle
+    xs, rep = run_batch(tiny, coef, 20, chunk_bytes=5 * 64 * 64 * 8, tune=-1, streams=2)
+    assert sorted((g["n"], g["haar_levels"], g["coil_images"]) for g in rep["groups"]) == \
+        [(64, 2, 3), (64, 3, 2), (64, 3, 4), (64, 3, 6), (128, 4, 3)]
+    for x, (xo, _, _) in zip(xs, ref):
         assert rel(x[None], xo) <= 1e-4
 
 
