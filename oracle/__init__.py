@@ -8,8 +8,13 @@ suite, by ``__graft_entry__.smoke()`` and by the CPU-baseline leg of
 ``bench.py``.  Nothing in the product library may call it.
 
 Pinned: every function here is checked in ``tests/test_oracle_*.py`` against
-closed forms, theorems of the paper, textbook definitions or brute force.
+closed forms, theorems of the paper, textbook definitions or brute force
+(finite differences for the derivatives of ``pfista_vjp``).
 """
 
 from .pfista_oracle import *  # noqa: F401,F403
-from .pfista_oracle import __all__  # noqa: F401
+from .pfista_oracle import __all__ as _ops_all
+from .pfista_vjp import *  # noqa: F401,F403
+from .pfista_vjp import __all__ as _vjp_all
+
+__all__ = list(_ops_all) + list(_vjp_all)
