@@ -215,6 +215,46 @@ int pfista_solve(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *ma
                  pfista_c32 *z_io, double *history, pfista_report *rep, void *ws,
                  hipStream_t stream);
 
+/* ------------------------------------------------------------ differentiation
+ * Algorithm 4 unrolled for a fixed iteration count K from x_0 = z_0 = 0,
+ * viewed as a map (lambda, c_0..c_d) -> x_K, and its reverse-mode derivative
+ * (for learning the threshold and the polynomial of Section 2.5 from data).
+ * The backward pass is hand-written: the prox pulls back through the Haar
+ * transform (orthonormal: its pull-back is its inverse) and the complex soft
+ * threshold (on its support the radial part of the cotangent passes unchanged
+ * and the tangential part is scaled by 1 - lambda/|u|; d w / d lambda =
+ * -u/|u|); the polynomial p(N') pulls back through the powers N'^i v_bar,
+ * i = 1..d, which also give dL/dc_i = -Re <N'^i v_bar, g_k> (N' is
+ * Hermitian).  Complex cotangents are real gradients packed as complex
+ * numbers (dL/dRe + i dL/dIm).  Iterates are checkpointed every ckpt_every
+ * iterations; the backward pass recomputes one segment at a time. */
+typedef struct {
+  double lambda;       /* >= 0 */
+  double inv_l;        /* 1/L > 0 */
+  int degree;          /* d >= 0 */
+  const double *coef;  /* HOST, degree+1 coefficients; NULL: L2-optimal fit */
+  int iters;           /* K >= 1 */
+  int ckpt_every;      /* >= 1 (values above K act as K) */
+  int momentum;        /* 1: FISTA momentum; 0: PGD / PPGD */
+} pfista_unroll_params;
+
+/* Device bytes of the checkpoint buffer filled by the forward pass and read
+ * by the backward pass: A'^H b' and (x_k, z_k) every ckpt_every iterations. */
+size_t pfista_unroll_ckpt_bytes(const pfista_plan *p, const pfista_unroll_params *prm);
+/* Device workspace of both passes (the plan's workspace plus the segment
+ * store, 3 * ckpt_every images, and d + 6 images of cotangents). */
+size_t pfista_unroll_workspace_bytes(const pfista_plan *p, const pfista_unroll_params *prm);
+/* x_out (device image) = x_K; fills ckpt.  Waits once for ||b||. */
+int pfista_unroll_forward(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *mask,
+                          const pfista_c32 *b, const pfista_unroll_params *prm, pfista_c32 *x_out,
+                          void *ckpt, void *ws, hipStream_t stream);
+/* Given x_bar = dL/dx_K (device image) and the forward's ckpt (same plan,
+ * sens, mask and params), writes grad (HOST, degree + 2 doubles):
+ * dL/dlambda, dL/dc_0 .. dL/dc_d.  Waits for the result. */
+int pfista_unroll_backward(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *mask,
+                           const pfista_unroll_params *prm, const pfista_c32 *x_bar,
+                           const void *ckpt, double *grad, void *ws, hipStream_t stream);
+
 /* ------------------------------------------------------------------ batches
  * A batch is a list of independent slices of uneven shape (image side, coil
  * count, Haar levels), each its own problem of the form above with its own

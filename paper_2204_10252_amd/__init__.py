@@ -17,7 +17,7 @@ __all__ = [
     "Plan", "PfistaError", "load_library", "library_path", "poly_coefficients",
     "poly_coefficients_weighted", "poly_coefficients_chebyshev", "normal_apply", "poly_apply", "step", "forward", "adjoint", "data_term",
     "power_iteration", "profile_normal", "solve", "MASK_2D", "MASK_1D", "header_functions",
-    "Batch", "batch_solve", "TUNE_CANDIDATES",
+    "Batch", "batch_solve", "TUNE_CANDIDATES", "Unrolled", "unrolled_pfista",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -78,6 +78,12 @@ class _BatchReport(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("status", ctypes.c_int), ("normal_applies", ctypes.c_longlong)]
 
 
+class _UnrollParams(ctypes.Structure):
+    _fields_ = [("lambda_", ctypes.c_double), ("inv_l", ctypes.c_double), ("degree", ctypes.c_int),
+                ("coef", ctypes.POINTER(ctypes.c_double)), ("iters", ctypes.c_int), ("ckpt_every", ctypes.c_int),
+                ("momentum", ctypes.c_int)]
+
+
 TUNE_CANDIDATES = 12
 
 _VP, _I, _F, _D = ctypes.c_void_p, ctypes.c_int, ctypes.c_float, ctypes.c_double
@@ -107,6 +113,11 @@ _SIGS = {
                                 ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_BatchParams),
                                 ctypes.POINTER(_VP), ctypes.POINTER(_SliceReport),
                                 ctypes.POINTER(_GroupReport), ctypes.POINTER(_BatchReport), _VP, _VP]),
+    "pfista_unroll_ckpt_bytes": (ctypes.c_size_t, [_VP, ctypes.POINTER(_UnrollParams)]),
+    "pfista_unroll_workspace_bytes": (ctypes.c_size_t, [_VP, ctypes.POINTER(_UnrollParams)]),
+    "pfista_unroll_forward": (_I, [_VP, _VP, _VP, _VP, ctypes.POINTER(_UnrollParams), _VP, _VP, _VP, _VP]),
+    "pfista_unroll_backward": (_I, [_VP, _VP, _VP, ctypes.POINTER(_UnrollParams), _VP, _VP,
+                                    ctypes.POINTER(_D), _VP, _VP]),
     "pfista_last_error": (ctypes.c_char_p, []),
 }
 
@@ -446,3 +457,92 @@ def batch_solve(batch, sens, mask, b, x, lam, degree=3, coef=None, max_iter=50, 
     out["groups"] = [{k: getattr(grep[i], k) for k, _ in _GroupReport._fields_} for i in range(batch.groups)]
     out["rc"] = rc
     return out
+
+
+# ------------------------------------------------------------------ differentiation
+
+class Unrolled:
+    """K unrolled iterations of Algorithm 4 on one plan, differentiable in the
+    threshold and the polynomial coefficients (``pfista_unroll_forward`` /
+    ``pfista_unroll_backward``).  Holds the checkpoint buffer of the last
+    forward pass and the workspace."""
+
+    def __init__(self, plan, degree, iters, inv_l, ckpt_every=5, momentum=True):
+        import torch
+        self.plan, self.degree, self.iters = plan, int(degree), int(iters)
+        self.inv_l, self.ckpt_every, self.momentum = float(inv_l), int(ckpt_every), bool(momentum)
+        lib = load_library()
+        prm = self._params(0.0, [0.0] * (self.degree + 1))
+        nck = int(lib.pfista_unroll_ckpt_bytes(plan.handle, ctypes.byref(prm)))
+        nws = int(lib.pfista_unroll_workspace_bytes(plan.handle, ctypes.byref(prm)))
+        if nck == 0 or nws == 0:
+            raise PfistaError(EINVAL, lib.pfista_last_error().decode() or "bad unroll parameters")
+        self.ckpt = torch.empty(nck, dtype=torch.uint8, device=plan.device)
+        self.ws = torch.empty(nws, dtype=torch.uint8, device=plan.device)
+
+    def _params(self, lam, coef):
+        self._carr = (ctypes.c_double * len(coef))(*[float(v) for v in coef])
+        return _UnrollParams(float(lam), self.inv_l, len(coef) - 1,
+                             ctypes.cast(self._carr, ctypes.POINTER(ctypes.c_double)), self.iters,
+                             self.ckpt_every, int(self.momentum))
+
+    def forward(self, sens, mask, b, x, lam, coef, stream=None):
+        c, pl = _cplx(), self.plan
+        if len(coef) != self.degree + 1:
+            raise ValueError(f"expected {self.degree + 1} coefficients")
+        prm = self._params(lam, coef)
+        _check(load_library().pfista_unroll_forward(
+            pl.handle, _ptr(sens, "sens", c, pl.n_coil), _ptr(mask, "mask", _u8(), pl.mask_numel),
+            _ptr(b, "b", c, pl.n_coil), ctypes.byref(prm), _ptr(x, "x", c, pl.n_img), _ptr(self.ckpt, "ckpt"),
+            _ptr(self.ws, "ws"), _stream(stream)))
+
+    def backward(self, sens, mask, x_bar, lam, coef, stream=None):
+        """(dL/dlambda, [dL/dc_0, ..., dL/dc_d]) for the cotangent x_bar."""
+        c, pl = _cplx(), self.plan
+        prm = self._params(lam, coef)
+        g = (ctypes.c_double * (self.degree + 2))()
+        _check(load_library().pfista_unroll_backward(
+            pl.handle, _ptr(sens, "sens", c, pl.n_coil), _ptr(mask, "mask", _u8(), pl.mask_numel),
+            ctypes.byref(prm), _ptr(x_bar, "x_bar", c, pl.n_img), _ptr(self.ckpt, "ckpt"), g,
+            _ptr(self.ws, "ws"), _stream(stream)))
+        return g[0], list(g)[1:]
+
+
+def _unrolled_function():
+    import torch
+
+    class _UnrolledPFISTA(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, lam, coef, unrolled, sens, mask, b):
+            pl = unrolled.plan
+            x = torch.empty((pl.slices, pl.n, pl.n), dtype=torch.complex64, device=sens.device)
+            lv, cv = float(lam), [float(v) for v in coef.detach().cpu()]
+            unrolled.forward(sens, mask, b, x, lv, cv)
+            ctx.unrolled, ctx.args = unrolled, (sens, mask, lv, cv)
+            ctx.dtypes = (lam.dtype, coef.dtype, lam.device, coef.device)
+            return x
+
+        @staticmethod
+        def backward(ctx, x_bar):
+            sens, mask, lv, cv = ctx.args
+            gl, gc = ctx.unrolled.backward(sens, mask, x_bar.contiguous(), lv, cv)
+            ld, cd, ldev, cdev = ctx.dtypes
+            return (torch.tensor(gl, dtype=ld, device=ldev), torch.tensor(gc, dtype=cd, device=cdev),
+                    None, None, None, None)
+
+    return _UnrolledPFISTA
+
+
+_UNROLLED_FN = None
+
+
+def unrolled_pfista(lam, coef, unrolled, sens, mask, b):
+    """x_K of ``unrolled`` (an ``Unrolled``) as a differentiable function of the
+    real tensors ``lam`` (0-d) and ``coef`` (d + 1), e.g.
+    ``loss(unrolled_pfista(lam, coef, u, sens, mask, b)).backward()``.  The
+    backward pass runs ``pfista_unroll_backward`` (it must follow the forward
+    pass of the same call, whose checkpoints it reads)."""
+    global _UNROLLED_FN
+    if _UNROLLED_FN is None:
+        _UNROLLED_FN = _unrolled_function()
+    return _UNROLLED_FN.apply(lam, coef, unrolled, sens, mask, b)

@@ -790,6 +790,145 @@ __global__ __launch_bounds__(64) void k_step(const float2 *__restrict__ z, const
 }
 
 // ---------------------------------------------------------------------------
+// Reverse mode of the prox step (the backward pass through unrolled iterations).
+// Complex cotangents are real gradients packed as complex numbers.
+// Pull-back of w = soft(u, lam) at u for the cotangent wb: on the support the
+// Jacobian (a map of R^2) keeps the direction u/|u| with factor 1 and scales the
+// perpendicular one by 1 - lam/|u|; dw/dlam = -u/|u| (accumulated in lb).
+__device__ __forceinline__ float2 soft_vjp(float2 u, float2 wb, float lam, float &lb) {
+  const float m2 = u.x * u.x + u.y * u.y;
+  const bool keep = m2 > lam * lam;
+  const float r = __builtin_amdgcn_rsqf(keep ? m2 : 1.0f);
+  const float ux = u.x * r, uy = u.y * r;
+  const float rad = ux * wb.x + uy * wb.y;
+  const float f = 1.0f - lam * r;
+  lb += keep ? -rad : 0.0f;
+  const float bx = rad * ux + f * (wb.x - rad * ux), by = rad * uy + f * (wb.y - rad * uy);
+  return keep ? make_float2(bx, by) : make_float2(0.f, 0.f);
+}
+
+// Levels l >= 2 of the pull-back, mirroring haar_levels: the group's analysis
+// of v (u) and of the cotangent (wb) side by side; returns this lane's LL
+// cotangent of level l - 1.
+template <int L, int LEVELS>
+__device__ __forceinline__ float2 haar_vjp_levels(float2 llu, float2 llw, int tx, int ty, float lam, float &lb) {
+  constexpr int st = 1 << (L - 2);
+  const int bx = (tx >> (L - 2)) & 1, by = (ty >> (L - 2)) & 1;
+  const float2 ux = shfl_xor2(llu, st), uy = shfl_xor2(llu, 8 * st), ud = shfl_xor2(llu, 9 * st);
+  const float2 wx = shfl_xor2(llw, st), wy = shfl_xor2(llw, 8 * st), wd = shfl_xor2(llw, 9 * st);
+  const Quad ru = haar4(pick4(bx, by, llu, ux, uy, ud), pick4(bx, by, ux, llu, ud, uy),
+                        pick4(bx, by, uy, ud, llu, ux), pick4(bx, by, ud, uy, ux, llu));
+  const Quad rw = haar4(pick4(bx, by, llw, wx, wy, wd), pick4(bx, by, wx, llw, wd, wy),
+                        pick4(bx, by, wy, wd, llw, wx), pick4(bx, by, wd, wy, wx, llw));
+  float lg = 0.f;   // identical in the four lanes of the group: counted once
+  Quad rb;
+  rb.dx = soft_vjp(ru.dx, rw.dx, lam, lg);
+  rb.dy = soft_vjp(ru.dy, rw.dy, lam, lg);
+  rb.dd = soft_vjp(ru.dd, rw.dd, lam, lg);
+  if constexpr (L == LEVELS) {
+    rb.ll = soft_vjp(ru.ll, rw.ll, lam, lg);
+  } else {
+    rb.ll = haar_vjp_levels<L + 1, LEVELS>(ru.ll, rw.ll, tx, ty, lam, lb);
+  }
+  if (!(tx & (2 * st - 1)) && !(ty & (2 * st - 1))) lb += lg;
+  float2 a, b, c, d;
+  ihaar4(rb, a, b, c, d);
+  return pick4(bx, by, a, b, c, d);
+}
+
+// Pull-back of one step x_(k+1) = prox(z_k - pg_k), z_(k+1) = (1 + beta) x_(k+1)
+// - beta x_k, given xb = x_bar_(k+1) and zb = z_bar_(k+1):
+//   vb = Psi^H J_soft(Psi v)^T Psi (xb + (1 + beta) zb),   v = z - pg,
+//   xb <- -beta zb  (x_bar_k, in place), FP64 partial sums of lambda_bar.
+template <int LEVELS>
+__global__ __launch_bounds__(64) void k_prox_vjp(const float2 *__restrict__ z, const float2 *__restrict__ pg,
+                                                 float2 *xb, const float2 *__restrict__ zb,
+                                                 float2 *__restrict__ vb, float lam, float beta, int N,
+                                                 double *__restrict__ partials) {
+  const int lane = threadIdx.x, tx = lane & 7, ty = lane >> 3;
+  const int s = blockIdx.z;
+  const int px = blockIdx.x * 16 + 2 * tx, py = blockIdx.y * 16 + 2 * ty;
+  const size_t o0 = (size_t)s * N * N + (size_t)py * N + px, o1 = o0 + N;
+  auto ld = [](const float2 *p, size_t o) { return *reinterpret_cast<const float4 *>(p + o); };
+  const float4 z0 = ld(z, o0), z1 = ld(z, o1), g0 = ld(pg, o0), g1 = ld(pg, o1);
+  const float4 x0 = ld(xb, o0), x1 = ld(xb, o1), q0 = ld(zb, o0), q1 = ld(zb, o1);
+  const float bz = 1.0f + beta;
+  const float2 va = make_float2(z0.x - g0.x, z0.y - g0.y), vbb = make_float2(z0.z - g0.z, z0.w - g0.w);
+  const float2 vc = make_float2(z1.x - g1.x, z1.y - g1.y), vd = make_float2(z1.z - g1.z, z1.w - g1.w);
+  const float2 wa = make_float2(x0.x + bz * q0.x, x0.y + bz * q0.y), wb = make_float2(x0.z + bz * q0.z, x0.w + bz * q0.w);
+  const float2 wc = make_float2(x1.x + bz * q1.x, x1.y + bz * q1.y), wd = make_float2(x1.z + bz * q1.z, x1.w + bz * q1.w);
+  const Quad qu = haar4(va, vbb, vc, vd), qw = haar4(wa, wb, wc, wd);
+  float lb = 0.f;
+  Quad rb;
+  rb.dx = soft_vjp(qu.dx, qw.dx, lam, lb);
+  rb.dy = soft_vjp(qu.dy, qw.dy, lam, lb);
+  rb.dd = soft_vjp(qu.dd, qw.dd, lam, lb);
+  if constexpr (LEVELS == 1) {
+    rb.ll = soft_vjp(qu.ll, qw.ll, lam, lb);
+  } else {
+    rb.ll = haar_vjp_levels<2, LEVELS>(qu.ll, qw.ll, tx, ty, lam, lb);
+  }
+  float2 ra, rbv, rc, rd;
+  ihaar4(rb, ra, rbv, rc, rd);
+  *reinterpret_cast<float4 *>(vb + o0) = make_float4(ra.x, ra.y, rbv.x, rbv.y);
+  *reinterpret_cast<float4 *>(vb + o1) = make_float4(rc.x, rc.y, rd.x, rd.y);
+  *reinterpret_cast<float4 *>(xb + o0) = make_float4(-beta * q0.x, -beta * q0.y, -beta * q0.z, -beta * q0.w);
+  *reinterpret_cast<float4 *>(xb + o1) = make_float4(-beta * q1.x, -beta * q1.y, -beta * q1.z, -beta * q1.w);
+  const double l = wave_sum((double)lb);
+  if (lane == 0) partials[((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = l;
+}
+
+// pv = sum_i c_i q_i over the d + 1 images q_i = q + i * n (q_0 = v_bar, q_i =
+// N'^i v_bar) and FP64 partial sums of Re <q_i, g>, (d + 1) per block.
+struct CoefArg { float c[9]; };
+__global__ __launch_bounds__(256) void k_poly_combine_dot(const float2 *__restrict__ q, int terms, size_t n,
+                                                          const float2 *__restrict__ g, CoefArg c,
+                                                          float2 *__restrict__ pv, double *__restrict__ partials) {
+  __shared__ double s_red[4][9];
+  double dot[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) dot[i] = 0.0;
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+    const float2 gv = g[e];
+    float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      if (i < terms) {
+        const float2 qi = q[(size_t)i * n + e];
+        acc.x += c.c[i] * qi.x;
+        acc.y += c.c[i] * qi.y;
+        dot[i] += (double)qi.x * gv.x + (double)qi.y * gv.y;
+      }
+    }
+    pv[e] = acc;
+  }
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    if (i < terms) {
+      const double v = wave_sum_d(dot[i]);
+      if (ln == 0) s_red[wv][i] = v;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < terms)
+    partials[(size_t)blockIdx.x * terms + threadIdx.x] =
+        ((s_red[0][threadIdx.x] + s_red[1][threadIdx.x]) + s_red[2][threadIdx.x]) + s_red[3][threadIdx.x];
+}
+
+// out[c] += scale * sum_i partials[i * width + c] for c < width <= 16, one wave,
+// fixed order
+__global__ __launch_bounds__(64) void k_reduce_add(const double *__restrict__ partials, int count, int width,
+                                                   double scale, double *__restrict__ out) {
+  for (int c = 0; c < width && c < 16; ++c) {
+    double a = 0.0;
+    for (int i = threadIdx.x; i < count; i += 64) a += partials[(size_t)i * width + c];
+    a = wave_sum_d(a);
+    if (threadIdx.x == 0) out[c] += scale * a;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Small helpers
 // Sum `width`-strided FP64 partials (width <= 4) in a fixed order into
 // out[0..width) with one wave: lane-strided sums, then a fixed butterfly.  If
@@ -840,6 +979,11 @@ __global__ __launch_bounds__(256) void k_norm2(const float2 *__restrict__ v, siz
     __syncthreads();
   }
   if (threadIdx.x == 0) partials[blockIdx.x] = s[0];
+}
+
+// the solver's iteration counter, set on the stream (no host memory involved)
+__global__ void k_set_counter(int *k, int v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *k = v;
 }
 
 __global__ __launch_bounds__(256) void k_fill(float2 *__restrict__ v, size_t n, float2 val) {

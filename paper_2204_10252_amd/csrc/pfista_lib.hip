@@ -1519,3 +1519,234 @@ int pfista_batch_solve(const pfista_batch *b, const pfista_c32 *const *sens, con
 }
 
 }  // extern "C"
+
+// ============================================================================ unrolled iterations
+namespace {
+
+struct ULayout {
+  Layout base;        // the plan's workspace (t, five images, partials, state)
+  size_t seg = 0;     // segment store: z_k, g_k, pg_k for ckpt_every steps
+  size_t q = 0;       // q_0 .. q_d, contiguous (stride n_img)
+  size_t pv = 0, xb = 0, zb = 0, zb2 = 0, x = 0, z = 0, cpart = 0, grad = 0, total = 0;
+  int ck = 1, nck = 1, ncomb = 1;
+};
+
+int check_unroll(const pfista_unroll_params *prm, std::vector<double> &c) {
+  if (!prm) return fail(PFISTA_EINVAL, "params is NULL");
+  if (prm->iters < 1) return fail(PFISTA_EINVAL, "iters must be >= 1");
+  if (prm->ckpt_every < 1) return fail(PFISTA_EINVAL, "ckpt_every must be >= 1");
+  if (!(prm->lambda >= 0.0) || !std::isfinite(prm->lambda)) return fail(PFISTA_EINVAL, "lambda must be finite and >= 0");
+  if (!(prm->inv_l > 0.0) || !std::isfinite(prm->inv_l)) return fail(PFISTA_EINVAL, "inv_l must be finite and > 0");
+  if (prm->coef) {
+    if (prm->degree < 0 || prm->degree > kMaxDegree) return fail(PFISTA_UNSUPPORTED, "degree %d", prm->degree);
+    c.assign(prm->coef, prm->coef + prm->degree + 1);
+    return PFISTA_OK;
+  }
+  return l2_coefficients(prm->degree, c);
+}
+
+ULayout ulayout(const pfista_desc &d, const pfista_unroll_params *prm) {
+  ULayout U;
+  U.base = layout(d);
+  const int deg = prm->coef ? prm->degree : std::max(0, std::min(prm->degree, kMaxDegree));
+  U.ck = std::max(1, std::min(prm->ckpt_every, prm->iters));
+  U.nck = (prm->iters + U.ck - 1) / U.ck;
+  const size_t img = U.base.n_img * sizeof(float2);
+  size_t off = U.base.total;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + std::max<size_t>(bytes, 1));
+    return o;
+  };
+  U.seg = take(3 * (size_t)U.ck * img);
+  U.q = take((size_t)(deg + 1) * img);
+  U.pv = take(img);
+  U.xb = take(img);
+  U.zb = take(img);
+  U.zb2 = take(img);
+  U.x = take(img);
+  U.z = take(img);
+  U.ncomb = (int)std::max<size_t>(1, std::min<size_t>(256, (U.base.n_img + 255) / 256));
+  U.cpart = take((size_t)U.ncomb * (deg + 1) * sizeof(double));
+  U.grad = take((size_t)(deg + 2) * sizeof(double));
+  U.total = off;
+  return U;
+}
+
+size_t ckpt_bytes(const pfista_desc &d, const ULayout &U) {
+  return (size_t)(1 + 2 * U.nck) * layout(d).n_img * sizeof(float2);
+}
+
+// the iteration counter the step kernel reads: the next chain advances it by one
+void set_counter(DevState *ds, int k, hipStream_t st) { pf::k_set_counter<<<1, 64, 0, st>>>(&ds->k, k); }
+
+// One forward step of Algorithm 4 from (x, z): writes g and pg, then x, z.
+void unroll_step(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *mask, const std::vector<double> &c,
+                 double inv_l, float lam, int use_k, const float2 *a, float2 *x, float2 *z, float2 *g, float2 *pg,
+                 void *ws, hipStream_t st) {
+  const Layout L = layout(p->d);
+  DevState *ds = at<DevState>(ws, L.state);
+  const int deg = (int)c.size() - 1;
+  grad_poly_op(p->d, sens, mask, inv_l, c, z, a, g, pg, ws, st, &ds->k);
+  if (deg == 0) pf::k_scale<<<blocks_for(L.n_img), 256, 0, st>>>(g, pg, L.n_img, (float)c[0]);
+  PF_DISPATCH(p->d.n, Ops<NN>::step(shape_of(p->d), z, pg, x, x, z, 1.f, lam, 0.f, &ds->k, use_k,
+                                    at<double>(ws, L.partials), st));
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pfista_unroll_ckpt_bytes(const pfista_plan *p, const pfista_unroll_params *prm) {
+  std::vector<double> c;
+  if (!p || check_unroll(prm, c) != PFISTA_OK) return 0;
+  pfista_unroll_params q = *prm;
+  q.degree = (int)c.size() - 1;
+  q.coef = c.data();
+  return ckpt_bytes(p->d, ulayout(p->d, &q));
+}
+
+size_t pfista_unroll_workspace_bytes(const pfista_plan *p, const pfista_unroll_params *prm) {
+  std::vector<double> c;
+  if (!p || check_unroll(prm, c) != PFISTA_OK) return 0;
+  pfista_unroll_params q = *prm;
+  q.degree = (int)c.size() - 1;
+  q.coef = c.data();
+  return ulayout(p->d, &q).total;
+}
+
+int pfista_unroll_forward(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *mask, const pfista_c32 *b,
+                          const pfista_unroll_params *prm, pfista_c32 *x_out, void *ckpt, void *ws,
+                          hipStream_t stream) {
+  PF_TRY(check_ops(p, sens, mask, ws));
+  std::vector<double> c;
+  PF_TRY(check_unroll(prm, c));
+  if (p->d.slices == 0) return PFISTA_OK;
+  PF_TRY(check_ptr(b, "b"));
+  PF_TRY(check_ptr(x_out, "x_out"));
+  PF_TRY(check_ptr(ckpt, "ckpt", 16));
+  pfista_unroll_params q = *prm;
+  q.degree = (int)c.size() - 1;
+  q.coef = c.data();
+  const ULayout U = ulayout(p->d, &q);
+  const size_t n = U.base.n_img;
+  if (n == 0) return PFISTA_OK;
+  DevState *ds = at<DevState>(ws, U.base.state);
+  double *partials = at<double>(ws, U.base.partials);
+  // ||b|| (the normalisation of Section 3), then a = A'^H b'
+  norm2_dev(F2(b), U.base.n_coil, partials, ds->misc, stream);
+  PF_TRY(launch_status("pfista_unroll_forward(norm)"));
+  double h = 0.0;
+  PF_HIP(hipMemcpyAsync(&h, ds->misc, sizeof(double), hipMemcpyDeviceToHost, stream));
+  PF_HIP(hipStreamSynchronize(stream));
+  const double bnorm = std::sqrt(h);
+  float2 *ck = static_cast<float2 *>(ckpt);
+  float2 *a = ck;
+  float2 *x = at<float2>(ws, U.x), *z = at<float2>(ws, U.z);
+  const double il = prm->inv_l;
+  PF_DISPATCH(p->d.n, Ops<NN>::adjoint(shape_of(p->d), F2(sens), mask, F2(b), a,
+                                       bnorm > 0.0 ? (float)(std::sqrt(il) / bnorm) : 0.f, at<float2>(ws, U.base.t),
+                                       stream));
+  pf::k_fill<<<blocks_for(n), 256, 0, stream>>>(x, n, make_float2(0.f, 0.f));
+  pf::k_fill<<<blocks_for(n), 256, 0, stream>>>(z, n, make_float2(0.f, 0.f));
+  set_counter(ds, -1, stream);
+  const int use_k = prm->momentum ? 1 : 0;
+  for (int k = 0; k < prm->iters; ++k) {
+    if (k % U.ck == 0) {
+      float2 *slot = ck + (size_t)(1 + 2 * (k / U.ck)) * n;
+      PF_HIP(hipMemcpyAsync(slot, x, n * sizeof(float2), hipMemcpyDeviceToDevice, stream));
+      PF_HIP(hipMemcpyAsync(slot + n, z, n * sizeof(float2), hipMemcpyDeviceToDevice, stream));
+    }
+    unroll_step(p, sens, mask, c, il, (float)prm->lambda, use_k, a, x, z, at<float2>(ws, U.base.img[1]),
+                at<float2>(ws, U.base.img[2]), ws, stream);
+  }
+  PF_HIP(hipMemcpyAsync(x_out, x, n * sizeof(float2), hipMemcpyDeviceToDevice, stream));
+  return launch_status("pfista_unroll_forward");
+}
+
+int pfista_unroll_backward(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *mask,
+                           const pfista_unroll_params *prm, const pfista_c32 *x_bar, const void *ckpt, double *grad,
+                           void *ws, hipStream_t stream) {
+  PF_TRY(check_ops(p, sens, mask, ws));
+  std::vector<double> c;
+  PF_TRY(check_unroll(prm, c));
+  if (!grad) return fail(PFISTA_EINVAL, "grad is NULL");
+  const int deg = (int)c.size() - 1;
+  for (int i = 0; i < deg + 2; ++i) grad[i] = 0.0;
+  if (p->d.slices == 0) return PFISTA_OK;
+  PF_TRY(check_ptr(x_bar, "x_bar"));
+  PF_TRY(check_ptr(ckpt, "ckpt", 16));
+  pfista_unroll_params q = *prm;
+  q.degree = deg;
+  q.coef = c.data();
+  const ULayout U = ulayout(p->d, &q);
+  const size_t n = U.base.n_img;
+  if (n == 0) return PFISTA_OK;
+  const pfista_desc &d = p->d;
+  DevState *ds = at<DevState>(ws, U.base.state);
+  double *partials = at<double>(ws, U.base.partials);
+  const float2 *ck = static_cast<const float2 *>(ckpt);
+  const float2 *a = ck;
+  float2 *x = at<float2>(ws, U.x), *z = at<float2>(ws, U.z);
+  float2 *seg = at<float2>(ws, U.seg);
+  float2 *qb = at<float2>(ws, U.q), *pv = at<float2>(ws, U.pv);
+  float2 *xb = at<float2>(ws, U.xb), *zb = at<float2>(ws, U.zb), *zb2 = at<float2>(ws, U.zb2);
+  double *gdev = at<double>(ws, U.grad), *cpart = at<double>(ws, U.cpart);
+  const double il = prm->inv_l;
+  const float lam = (float)prm->lambda;
+  const int use_k = prm->momentum ? 1 : 0;
+  PF_HIP(hipMemsetAsync(gdev, 0, (size_t)(deg + 2) * sizeof(double), stream));
+  PF_HIP(hipMemcpyAsync(xb, x_bar, n * sizeof(float2), hipMemcpyDeviceToDevice, stream));
+  pf::k_fill<<<blocks_for(n), 256, 0, stream>>>(zb, n, make_float2(0.f, 0.f));
+  pf::CoefArg carg{};
+  for (int i = 0; i <= deg && i < 9; ++i) carg.c[i] = (float)c[i];
+  float alpha[kMaxDegree + 1], beta0[kMaxDegree + 1];
+  const float2 *wnull[kMaxDegree + 1];
+  float2 *qy[kMaxDegree + 1];
+  for (int i = 0; i < deg; ++i) {
+    alpha[i] = (float)il;
+    beta0[i] = 0.f;
+    wnull[i] = nullptr;
+    qy[i] = qb + (size_t)(i + 1) * n;
+  }
+  const dim3 sgrid(d.n / 16, d.n / 16, d.slices);
+  const int nsb = (d.n / 16) * (d.n / 16) * d.slices;
+  for (int j = U.nck - 1; j >= 0; --j) {
+    const int k0 = j * U.ck, k1 = std::min(k0 + U.ck, prm->iters);
+    // recompute the segment from its checkpoint, keeping z_k, g_k, pg_k
+    PF_HIP(hipMemcpyAsync(x, ck + (size_t)(1 + 2 * j) * n, n * sizeof(float2), hipMemcpyDeviceToDevice, stream));
+    PF_HIP(hipMemcpyAsync(z, ck + (size_t)(2 + 2 * j) * n, n * sizeof(float2), hipMemcpyDeviceToDevice, stream));
+    set_counter(ds, k0 - 1, stream);
+    for (int k = k0; k < k1; ++k) {
+      float2 *sz = seg + (size_t)(3 * (k - k0)) * n;
+      PF_HIP(hipMemcpyAsync(sz, z, n * sizeof(float2), hipMemcpyDeviceToDevice, stream));
+      unroll_step(p, sens, mask, c, il, lam, use_k, a, x, z, sz + n, sz + 2 * n, ws, stream);
+    }
+    // pull back through the segment's steps in reverse order
+    for (int k = k1 - 1; k >= k0; --k) {
+      const float2 *sz = seg + (size_t)(3 * (k - k0)) * n;
+      const float beta = prm->momentum ? (float)((double)k / ((double)k + 3.0)) : 0.f;
+      switch (d.haar_levels) {
+        case 1: pf::k_prox_vjp<1><<<sgrid, 64, 0, stream>>>(sz, sz + 2 * n, xb, zb, qb, lam, beta, d.n, partials); break;
+        case 2: pf::k_prox_vjp<2><<<sgrid, 64, 0, stream>>>(sz, sz + 2 * n, xb, zb, qb, lam, beta, d.n, partials); break;
+        case 3: pf::k_prox_vjp<3><<<sgrid, 64, 0, stream>>>(sz, sz + 2 * n, xb, zb, qb, lam, beta, d.n, partials); break;
+        default: pf::k_prox_vjp<4><<<sgrid, 64, 0, stream>>>(sz, sz + 2 * n, xb, zb, qb, lam, beta, d.n, partials); break;
+      }
+      pf::k_reduce_add<<<1, 64, 0, stream>>>(partials, nsb, 1, 1.0, gdev);
+      if (deg > 0)
+        PF_DISPATCH(d.n, Ops<NN>::chain(shape_of(d), F2(sens), mask, qb, deg, alpha, beta0, wnull, qy,
+                                        at<float2>(ws, U.base.t), stream, nullptr));
+      pf::k_poly_combine_dot<<<U.ncomb, 256, 0, stream>>>(qb, deg + 1, n, sz + n, carg, pv, cpart);
+      pf::k_reduce_add<<<1, 64, 0, stream>>>(cpart, U.ncomb, deg + 1, -1.0, gdev + 1);
+      // z_bar_k = v_bar - N' p(N') v_bar
+      normal_op(d, sens, mask, pv, zb2, (float)(-il), qb, 1.f, ws, stream);
+      std::swap(zb, zb2);
+    }
+    PF_TRY(launch_status("pfista_unroll_backward"));
+  }
+  PF_HIP(hipMemcpyAsync(grad, gdev, (size_t)(deg + 2) * sizeof(double), hipMemcpyDeviceToHost, stream));
+  PF_HIP(hipStreamSynchronize(stream));
+  return PFISTA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,166 @@
+"""GPU parity of the derivative of unrolled PFISTA (dL/dlambda, dL/dc_i)
+against the FP64 oracle's pull-back, plus the torch autograd wrapper.
+
+Both sides get the same complex64 inputs, the same inv_l (oracle power
+iteration) and the same cotangent.  Bars: x_K within 1e-4 (the solve's bar);
+every gradient component within 1e-3 of the largest one (a K-step chain of
+FP32 applies and thresholds, each within ~1e-5, feeds the pull-back; the FP32
+threshold decisions agree with FP64 except at coefficients within rounding of
+lambda, whose contribution is continuous).
+"""
+
+import numpy as np
+import pytest
+
+import oracle as orc
+from synth import make_inputs, power_start_vector
+from tests.gpu_util import c64, rel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def problem(wid, power_iters=60):
+    inp = make_inputs(wid)
+    sens = c64(inp["sens"])
+    s128 = sens.astype(np.complex128)
+    b = c64(orc.kspace_data(s128, inp["mask"], inp["phantom"], inp["noise"]))
+    lam_max = orc.power_iteration(s128, inp["mask"], power_start_vector(inp["n"], inp["slices"]), power_iters)
+    inv_l = 1.0 / (1.01 * lam_max)
+    bn = b.astype(np.complex128) / np.linalg.norm(b.astype(np.complex128))
+    return inp, sens, s128, b, bn, inv_l
+
+
+@pytest.fixture(scope="module")
+def w1():
+    return problem(1)
+
+
+def gpu_unrolled(inp, degree, iters, inv_l, ckpt_every=5, momentum=True):
+    import paper_2204_10252_amd as pf
+    plan = pf.Plan(inp["n"], inp["coils"], inp["slices"], haar_levels=inp["levels"])
+    return pf.Unrolled(plan, degree, iters, inv_l, ckpt_every=ckpt_every, momentum=momentum)
+
+
+def coefs(degree):
+    return [1.0] if degree == 0 else [float(c) for c in orc.l2_poly_coefficients(degree)]
+
+
+@pytest.mark.parametrize("degree,momentum", [(3, True), (0, True), (1, True), (2, False)])
+def test_gradient_matches_oracle(w1, degree, momentum):
+    import torch
+    inp, sens, s128, b, bn, inv_l = w1
+    K, lam = 12, inp["lam"]
+    coef = coefs(degree)
+    u = gpu_unrolled(inp, degree, K, inv_l, momentum=momentum)
+    ts, tm, tb = to_dev(sens), to_dev(inp["mask"]), to_dev(b)
+    x = torch.empty((1, inp["n"], inp["n"]), dtype=torch.complex64, device="cuda")
+    u.forward(ts, tm, tb, x, lam, coef)
+    xo, _ = orc.unrolled_forward(s128, inp["mask"], bn, inv_l, lam, coef, inp["levels"], K, momentum)
+    assert rel(x.cpu().numpy(), xo) <= 1e-4
+    rng = np.random.default_rng(5)
+    xbar = c64(rng.standard_normal(xo.shape) + 1j * rng.standard_normal(xo.shape))
+    gl, gc = u.backward(ts, tm, to_dev(xbar), lam, coef)
+    ol, oc = orc.unrolled_vjp(s128, inp["mask"], bn, inv_l, lam, coef, inp["levels"], K,
+                              xbar.astype(np.complex128), momentum)
+    want = np.concatenate([[ol], oc])
+    got = np.concatenate([[gl], gc])
+    print("grad gpu", got, "oracle", want, flush=True)
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-3 * np.abs(want).max())
+
+
+def test_checkpoint_interval_does_not_change_the_gradient(w1):
+    import torch
+    inp, sens, s128, b, bn, inv_l = w1
+    coef = coefs(2)
+    ts, tm, tb = to_dev(sens), to_dev(inp["mask"]), to_dev(b)
+    rng = np.random.default_rng(6)
+    xbar = to_dev(c64(rng.standard_normal((1, 64, 64)) + 1j * rng.standard_normal((1, 64, 64))))
+    res = []
+    for ck in (1, 3, 5, 11, 50):
+        u = gpu_unrolled(inp, 2, 11, inv_l, ckpt_every=ck)
+        x = torch.empty((1, 64, 64), dtype=torch.complex64, device="cuda")
+        u.forward(ts, tm, tb, x, inp["lam"], coef)
+        res.append((x.cpu().numpy(), u.backward(ts, tm, xbar, inp["lam"], coef)))
+    for xr, g in res[1:]:
+        assert np.array_equal(xr, res[0][0])
+        assert g == res[0][1]
+
+
+def test_autograd_mse_to_phantom(w1):
+    # loss = mean |s x_K - phantom|^2 with s = sqrt(inv_l) ||b|| (x_K in original units)
+    import torch
+    import paper_2204_10252_amd as pf
+    inp, sens, s128, b, bn, inv_l = w1
+    K, degree = 10, 3
+    u = gpu_unrolled(inp, degree, K, inv_l)
+    scale = np.sqrt(inv_l) * np.linalg.norm(b.astype(np.complex128))
+    lam = torch.tensor(inp["lam"], dtype=torch.float64, requires_grad=True)
+    coef = torch.tensor(coefs(degree), dtype=torch.float64, requires_grad=True)
+    ph = to_dev(c64(inp["phantom"]))
+    x = pf.unrolled_pfista(lam, coef, u, to_dev(sens), to_dev(inp["mask"]), to_dev(b))
+    loss = torch.mean(torch.abs(scale * x - ph) ** 2)
+    loss.backward()
+    # oracle: the same loss, cotangent dL/dRe x + i dL/dIm x = 2 s (s x - phantom) / M
+    xo, _ = orc.unrolled_forward(s128, inp["mask"], bn, inv_l, inp["lam"], coefs(degree), inp["levels"], K)
+    xbar = 2.0 * scale * (scale * xo - inp["phantom"]) / xo.size
+    ol, oc = orc.unrolled_vjp(s128, inp["mask"], bn, inv_l, inp["lam"], coefs(degree), inp["levels"], K, xbar)
+    want = np.concatenate([[ol], oc])
+    got = np.concatenate([[lam.grad.item()], coef.grad.numpy()])
+    print("autograd", got, "oracle", want, flush=True)
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-3 * np.abs(want).max())
+    assert loss.item() == pytest.approx(float(np.mean(np.abs(scale * xo - inp["phantom"]) ** 2)), rel=1e-4)
+
+
+def test_unrolled_rejects_bad_parameters(w1):
+    import paper_2204_10252_amd as pf
+    inp, sens, s128, b, bn, inv_l = w1
+    with pytest.raises(pf.PfistaError):
+        gpu_unrolled(inp, 2, 0, inv_l)
+    with pytest.raises(pf.PfistaError):
+        gpu_unrolled(inp, 2, 5, 0.0)
+
+
+def test_workload5_full_size():
+    # 8 slices 192 x 192, 12 coils, R = 5, d = 4, 20 unrolled iterations,
+    # checkpoints every 5; MSE to the phantom
+    import torch
+    import paper_2204_10252_amd as pf
+    inp, sens, s128, b, bn, inv_l = problem(5, power_iters=30)
+    K, degree = 20, 4
+    u = gpu_unrolled(inp, degree, K, inv_l, ckpt_every=5)
+    scale = np.sqrt(inv_l) * np.linalg.norm(b.astype(np.complex128))
+    ts, tm, tb = to_dev(sens), to_dev(inp["mask"]), to_dev(b)
+    ph = to_dev(c64(inp["phantom"]))
+
+    def loss_of(lv, cv):
+        lam = torch.tensor(lv, dtype=torch.float64, requires_grad=True)
+        coef = torch.tensor(cv, dtype=torch.float64, requires_grad=True)
+        x = pf.unrolled_pfista(lam, coef, u, ts, tm, tb)
+        loss = torch.mean(torch.abs(scale * x - ph) ** 2)
+        return loss, lam, coef, x
+
+    c0 = coefs(degree)
+    loss, lam, coef, x = loss_of(inp["lam"], c0)
+    loss.backward()
+    got = np.concatenate([[lam.grad.item()], coef.grad.numpy()])
+    xo, _ = orc.unrolled_forward(s128, inp["mask"], bn, inv_l, inp["lam"], c0, inp["levels"], K)
+    assert rel(x.detach().cpu().numpy(), xo) <= 1e-4
+    xbar = 2.0 * scale * (scale * xo - inp["phantom"]) / xo.size
+    ol, oc = orc.unrolled_vjp(s128, inp["mask"], bn, inv_l, inp["lam"], c0, inp["levels"], K, xbar)
+    want = np.concatenate([[ol], oc])
+    print("W5 grad gpu", got, "oracle", want, flush=True)
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-3 * np.abs(want).max())
+    # central differences of the FP32 forward, step 1e-3 relative: a coarse check
+    # (the loss has threshold kinks at every scale, so the slope is averaged)
+    theta = np.array([inp["lam"]] + c0)
+    for j in range(theta.size):
+        h = 1e-3 * abs(theta[j])
+        tp, tm_ = theta.copy(), theta.copy()
+        tp[j] += h
+        tm_[j] -= h
+        with torch.no_grad():
+            lp = loss_of(tp[0], list(tp[1:]))[0].item()
+            lm = loss_of(tm_[0], list(tm_[1:]))[0].item()
+        fd = (lp - lm) / (2 * h)
+        print(f"W5 fd[{j}] {fd:.6e} analytic {got[j]:.6e}", flush=True)
+        assert fd == pytest.approx(got[j], rel=5e-2, abs=5e-3 * np.abs(got).max())
