@@ -20,6 +20,8 @@ iterations (inputs resident in HBM, graph-replayed loop).  Also reported:
 * the batch workload (64 uneven slices): the batched solver's loop time with
   tuned and default launch shapes, 1 and 4 concurrent branches, against
   solving the slices one plan at a time;
+* the differentiation workload (8 slices 192 x 192, 12 coils, 20 unrolled
+  degree-4 iterations): forward and hand-written backward pass times;
 * the FP64 oracle timed on the host cores on a bounded sample (cpu_baseline).
 
 Prints one JSON line on stdout; progress goes to stderr.
@@ -323,6 +325,56 @@ def batch_benchmark(torch, pf, dev, stream, graph_iters=10, k_short=10, k_long=6
     return out
 
 
+def grad_benchmark(torch, pf, dev, stream, reps=5):
+    """Workload 5: 8 slices 192 x 192, 12 coils, R = 5, degree 4, 20 unrolled
+    iterations with checkpoints every 5; forward pass and the hand-written
+    backward pass (dL/dlambda and dL/dc_0..c_4 of the MSE to the phantom)."""
+    import numpy as np
+
+    from synth import WORKLOADS, make_inputs
+    w = WORKLOADS[5]
+    inp = make_inputs(5)
+    n, C, S = inp["n"], inp["coils"], inp["slices"]
+    plan = pf.Plan(n, C, S, haar_levels=inp["levels"], device=dev)
+    sens = torch.from_numpy(inp["sens"].astype(np.complex64)).to(dev)
+    mask = torch.from_numpy(inp["mask"]).to(dev)
+    img = torch.from_numpy(inp["phantom"].astype(np.complex64)).to(dev)
+    b = torch.empty((S, C, n, n), dtype=torch.complex64, device=dev)
+    pf.forward(plan, sens, mask, img, b)
+    b += torch.from_numpy(inp["noise"].astype(np.complex64)).to(dev) * mask[:, None].to(torch.complex64)
+    inv_l = 1.0 / (1.01 * pf.power_iteration(plan, sens, mask, 30))
+    K, d = w.iters, w.degree
+    u = pf.Unrolled(plan, d, K, inv_l, ckpt_every=5)
+    coef = pf.poly_coefficients(d)
+    scale = float(np.sqrt(inv_l) * torch.linalg.vector_norm(b).item())
+    x = torch.empty((S, n, n), dtype=torch.complex64, device=dev)
+    tf, tb = [], []
+    with torch.cuda.stream(stream):
+        for r in range(reps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            u.forward(sens, mask, b, x, w.lam, coef, stream=stream)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            xbar = (2.0 * scale / x.numel()) * (scale * x - img)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            grad = u.backward(sens, mask, xbar, w.lam, coef, stream=stream)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            if r > 0:
+                tf.append(t1 - t0)
+                tb.append(t3 - t2)
+    fwd, bwd = sorted(tf)[len(tf) // 2], sorted(tb)[len(tb) // 2]
+    applies_f, applies_b = K * (d + 1), 2 * K * (d + 1)
+    return {"workload": "8 slices 192x192, 12 coils, R=5, d=4, 20 unrolled iterations, checkpoints every 5",
+            "forward_ms": round(1e3 * fwd, 3), "backward_ms": round(1e3 * bwd, 3),
+            "backward_over_forward": round(bwd / fwd, 3),
+            "applies_forward": applies_f, "applies_backward": applies_b,
+            "applies_per_s": round((applies_f + applies_b) / (fwd + bwd), 1),
+            "grad_lambda": grad[0], "grad_coef": grad[1]}
+
+
 def cpu_baseline(inp, degree, seconds):
     """The FP64 oracle's PFISTA iterations on the host, for a bounded time."""
     import numpy as np
@@ -358,6 +410,7 @@ def main():
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-tolerance comparison")
     ap.add_argument("--no-slab", action="store_true", help="skip the 32-slice slab workload")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-slice uneven batch workload")
+    ap.add_argument("--no-grad", action="store_true", help="skip the differentiation workload")
     ap.add_argument("--profile-only", action="store_true",
                     help="only the per-pass kernel timing (for a matching rocprofv3 kernel-trace run)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -451,6 +504,13 @@ def main():
         batch = batch_benchmark(torch, pf, dev, stream, graph_iters=args.graph_iters)
         log(f"batch: {batch['configs']}, looped single-slice {batch['looped_single_slice']}")
 
+    grad = None
+    if not args.no_grad:
+        log("differentiation workload")
+        torch.cuda.empty_cache()
+        grad = grad_benchmark(torch, pf, dev, stream)
+        log(f"grad: {grad}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"cpu baseline ({args.cpu_seconds:.0f} s)")
@@ -477,6 +537,7 @@ def main():
         "time_to_tol": ttt,
         "slab": slab,
         "batch": batch,
+        "grad": grad,
     }
     print(json.dumps(out), flush=True)
 

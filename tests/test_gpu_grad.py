@@ -6,7 +6,8 @@ iteration) and the same cotangent.  Bars: x_K within 1e-4 (the solve's bar);
 every gradient component within 1e-3 of the largest one (a K-step chain of
 FP32 applies and thresholds, each within ~1e-5, feeds the pull-back; the FP32
 threshold decisions agree with FP64 except at coefficients within rounding of
-lambda, whose contribution is continuous).
+lambda, whose contribution is continuous), checked separately for dL/dlambda and
+for the coefficient gradient.
 """
 
 import numpy as np
@@ -41,6 +42,12 @@ def gpu_unrolled(inp, degree, iters, inv_l, ckpt_every=5, momentum=True):
     return pf.Unrolled(plan, degree, iters, inv_l, ckpt_every=ckpt_every, momentum=momentum)
 
 
+def close(got, want):
+    """dL/dlambda within 1e-3 relative; dL/dc within 1e-3 of its largest entry."""
+    assert abs(got[0] - want[0]) <= 1e-3 * abs(want[0])
+    np.testing.assert_allclose(got[1:], want[1:], rtol=1e-3, atol=1e-3 * np.abs(want[1:]).max())
+
+
 def coefs(degree):
     return [1.0] if degree == 0 else [float(c) for c in orc.l2_poly_coefficients(degree)]
 
@@ -65,7 +72,7 @@ def test_gradient_matches_oracle(w1, degree, momentum):
     want = np.concatenate([[ol], oc])
     got = np.concatenate([[gl], gc])
     print("grad gpu", got, "oracle", want, flush=True)
-    np.testing.assert_allclose(got, want, rtol=0, atol=1e-3 * np.abs(want).max())
+    close(got, want)
 
 
 def test_checkpoint_interval_does_not_change_the_gradient(w1):
@@ -107,7 +114,7 @@ def test_autograd_mse_to_phantom(w1):
     want = np.concatenate([[ol], oc])
     got = np.concatenate([[lam.grad.item()], coef.grad.numpy()])
     print("autograd", got, "oracle", want, flush=True)
-    np.testing.assert_allclose(got, want, rtol=0, atol=1e-3 * np.abs(want).max())
+    close(got, want)
     assert loss.item() == pytest.approx(float(np.mean(np.abs(scale * xo - inp["phantom"]) ** 2)), rel=1e-4)
 
 
@@ -149,12 +156,12 @@ def test_workload5_full_size():
     ol, oc = orc.unrolled_vjp(s128, inp["mask"], bn, inv_l, inp["lam"], c0, inp["levels"], K, xbar)
     want = np.concatenate([[ol], oc])
     print("W5 grad gpu", got, "oracle", want, flush=True)
-    np.testing.assert_allclose(got, want, rtol=0, atol=1e-3 * np.abs(want).max())
-    # central differences of the FP32 forward, step 1e-3 relative: a coarse check
-    # (the loss has threshold kinks at every scale, so the slope is averaged)
+    close(got, want)
+    # central differences of the FP32 forward: step 1e-3 on each coefficient,
+    # 1e-3 relative on lambda (lambda itself is 5e-4)
     theta = np.array([inp["lam"]] + c0)
     for j in range(theta.size):
-        h = 1e-3 * abs(theta[j])
+        h = 1e-3 * abs(theta[j]) if j == 0 else 1e-3
         tp, tm_ = theta.copy(), theta.copy()
         tp[j] += h
         tm_[j] -= h
@@ -163,4 +170,4 @@ def test_workload5_full_size():
             lm = loss_of(tm_[0], list(tm_[1:]))[0].item()
         fd = (lp - lm) / (2 * h)
         print(f"W5 fd[{j}] {fd:.6e} analytic {got[j]:.6e}", flush=True)
-        assert fd == pytest.approx(got[j], rel=5e-2, abs=5e-3 * np.abs(got).max())
+        assert fd == pytest.approx(got[j], rel=2e-2)
