@@ -14,7 +14,9 @@ closed forms, theorems of the paper, textbook definitions or brute force
 
 from .pfista_oracle import *  # noqa: F401,F403
 from .pfista_oracle import __all__ as _ops_all
+from .pfista_toeplitz import *  # noqa: F401,F403
+from .pfista_toeplitz import __all__ as _toe_all
 from .pfista_vjp import *  # noqa: F401,F403
 from .pfista_vjp import __all__ as _vjp_all
 
-__all__ = list(_ops_all) + list(_vjp_all)
+__all__ = list(_ops_all) + list(_vjp_all) + list(_toe_all)

@@ -192,6 +192,26 @@ def complex_noise(shape, sigma: float, rng: np.random.Generator) -> np.ndarray:
     return sigma * (re + 1j * im)
 
 
+def spiral_trajectory(n: int, interleaves: int, samples: int, turns: float, power: float,
+                      rng: np.random.Generator) -> np.ndarray:
+    """Variable-density spiral k-space trajectory, float64 ``[interleaves * samples, 2]``
+    (kx, ky) in cycles per field of view (|k| <= n/2).
+
+    Interleave i starts at angle ``2 pi i / interleaves`` plus one random rotation
+    shared by all interleaves; sample t = 1..samples of an interleave sits at radius
+    ``(n/2) (t/samples)^power`` and angle ``2 pi turns t/samples`` further on, so
+    ``power > 1`` samples the centre more densely than the edge.
+    """
+    rot = rng.uniform(0.0, 2.0 * np.pi)
+    t = np.arange(1, samples + 1) / samples
+    r = 0.5 * n * t ** power
+    out = []
+    for i in range(interleaves):
+        ang = rot + 2.0 * np.pi * i / interleaves + 2.0 * np.pi * turns * t
+        out.append(np.stack([r * np.cos(ang), r * np.sin(ang)], axis=1))
+    return np.concatenate(out, axis=0)
+
+
 def power_start_vector(n: int, slices: int = 1, seed: int = 0) -> np.ndarray:
     """Unit-norm complex Gaussian start vector ``[slices, n, n]`` for power iteration."""
     rng = np.random.default_rng(seed)

@@ -8,7 +8,8 @@ with seeded synthetic content.
 
 Seeds: slice ``s`` of workload ``w`` (1-based) uses ``default_rng(1000*w + s)``,
 drawing in the order: per-slice shape parameters (batched workload only),
-phantom, coil maps, mask, noise.
+phantom, coil maps, mask (or spiral trajectory), noise.  For the spiral
+workload ``mask`` holds the trajectory ``[J, 2]`` and ``noise`` is ``[C, J]``.
 """
 
 from __future__ import annotations
@@ -51,6 +52,9 @@ WORKLOADS = {
                  "accel_range": (3.0, 8.0), "lam_range": (2e-4, 2e-3)}),
     5: Workload(5, "batch of 8 slices 192x192, 12 coils", 192, 12, 8, "vd", 5.0, 24,
                 5e-3, 4, 5e-4, 4, 20),
+    6: Workload(6, "non-Cartesian 256x256, 12 coils, variable-density spiral", 256, 12, 1, "spiral",
+                None, None, 5e-3, 4, 5e-4, 3, 200,
+                {"interleaves": 16, "samples": 1024, "turns": 8.0, "power": 1.5}),
 }
 
 
@@ -75,12 +79,16 @@ def make_slice_inputs(wid: int, s: int) -> dict:
     elif w.mask == "pe1d":
         n_rand = w.extra["n_random_lines"]
         mask = g.mask_phase_encode_1d(n, centre, n_rand, rng)
+    elif w.mask == "spiral":
+        e = w.extra
+        mask = g.spiral_trajectory(n, e["interleaves"], e["samples"], e["turns"], e["power"], rng)
     else:
         raise ValueError(w.mask)
-    noise = g.complex_noise((coils, n, n), w.sigma, rng)
+    noise = g.complex_noise((coils, mask.shape[0]) if w.mask == "spiral" else (coils, n, n), w.sigma, rng)
     return {"phantom": img, "sens": sens, "mask": mask, "noise": noise, "n": n,
             "coils": coils, "lam": lam, "accel": accel, "levels": w.levels,
-            "degree": w.degree, "mask_kind": "1d" if w.mask == "pe1d" else "2d"}
+            "degree": w.degree,
+            "mask_kind": {"pe1d": "1d", "spiral": "spiral"}.get(w.mask, "2d")}
 
 
 def make_inputs(wid: int, slices: int | None = None) -> dict:
