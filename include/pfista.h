@@ -61,7 +61,13 @@ typedef enum {
   PFISTA_DIVERGED = -4     /* non-finite or exploding objective in pfista_solve */
 } pfista_status;
 
-typedef enum { PFISTA_MASK_2D = 0, PFISTA_MASK_1D = 1 } pfista_mask_kind;
+/* Operator kind of a plan.  2D / 1D: Cartesian sampling, `mask` as in the
+ * header.  TOEPLITZ: non-Cartesian sampling (Section 3.3), whose normal
+ * operator E^H E (E the non-uniform DFT of a trajectory) is applied through
+ * its Toeplitz structure as a 2n x 2n circular convolution; every `mask`
+ * argument of such a plan is the real kernel float [S][2n][2n] that
+ * pfista_toeplitz_kernel builds (n in {64, 128, 160, 192, 256}). */
+typedef enum { PFISTA_MASK_2D = 0, PFISTA_MASK_1D = 1, PFISTA_TOEPLITZ = 2 } pfista_mask_kind;
 
 /* Problem shape.  n in {64, 128, 160, 192, 256, 320, 384, 512} (radices 2, 3,
  * 5); 1 <= haar_levels <= 4; coils >= 1; slices >= 0; slices * coils <= 65535. */
@@ -117,7 +123,9 @@ int pfista_step(const pfista_plan *p, const pfista_c32 *z, const pfista_c32 *pg,
                 const pfista_c32 *x_old, pfista_c32 *x_new, pfista_c32 *z_new, float lambda,
                 float beta_k, double *red, void *ws, hipStream_t stream);
 
-/* Forward model: kspace = M F (S x), zero off-mask. */
+/* Forward model: kspace = M F (S x), zero off-mask.  Cartesian plans only
+ * (UNSUPPORTED for Toeplitz plans, as are pfista_adjoint and pfista_data_term:
+ * their data lives off the grid, see pfista_nudft_*). */
 int pfista_forward(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *mask,
                    const pfista_c32 *x, pfista_c32 *kspace, void *ws, hipStream_t stream);
 
@@ -187,6 +195,9 @@ typedef struct {
                           iterations (needs a non-default stream); 0: launches */
   int momentum;        /* 1: FISTA momentum (Algorithms 2 and 4); 0: none, i.e.
                           PGD / PPGD (Algorithms 1 and 3) */
+  double bnorm;        /* Toeplitz plans: ||b|| of the non-Cartesian data (> 0);
+                          their `b` argument is the image A^H b [S][N][N].
+                          Ignored by Cartesian plans (they compute ||b||). */
 } pfista_params;
 
 typedef struct {
@@ -209,11 +220,36 @@ typedef struct {
  * image for the momentum point (may be NULL when k0 == 0).  history (HOST,
  * nullable): F(x) after each check, ceil(max_iter / check_every) doubles, when
  * eval_objective.  Returns DIVERGED (and stops) on a non-finite value or an
- * objective above 10 F(0) = 5. */
+ * objective above 10 F(0) = 5.  Toeplitz plans: `b` is the image A^H b and
+ * params.bnorm = ||b||; the data term at checks is evaluated through the
+ * normal equations, <x, N'x> - 2 Re <x, A'^H b'> + 1 (one more apply). */
 int pfista_solve(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *mask,
                  const pfista_c32 *b, const pfista_params *prm, pfista_c32 *x_io,
                  pfista_c32 *z_io, double *history, pfista_report *rep, void *ws,
                  hipStream_t stream);
+
+/* ---------------------------------------------------------------- non-Cartesian
+ * Trajectories are float [S][J][2] (kx, ky) in cycles per field of view
+ * (|k| <= n/2); the non-uniform DFT of slice s is
+ *   (E v)_j = (1/n) sum_(y,x) v[y][x] exp(-2 pi i (kx_j x + ky_j y) / n),
+ * which on integer points is the unitary DFT of the Cartesian model.  The
+ * Toeplitz kernel is
+ *   K[ky][kx] = (1/n^2) sum_j w_j D(kx_j/n - kx/(2n)) D(ky_j/n - ky/(2n)),
+ *   D(u) = sin((2n - 1) pi u) / sin(pi u),
+ * the 2n-point DFT of the difference kernel of E^H W E (W = diag(w), w = 1
+ * when `weights` is NULL), so that for a Toeplitz plan
+ *   A'^H A' x = inv_l sum_c conj(S_c) crop(IDFT(K DFT(pad(S_c x)))).
+ * All three calls are set-up work (FP64 sums, O(J n^2) per slice), enqueued
+ * on `stream`; plan must be a Toeplitz plan; errors EINVAL on NULL, J < 1. */
+/* kern: device float [S][2n][2n]; weights: device float [S][J] or NULL. */
+int pfista_toeplitz_kernel(const pfista_plan *p, const float *traj, const float *weights, int J,
+                           float *kern, hipStream_t stream);
+/* kdata[s][c][j] = (E (S_c x_s))_j: device [S][C][J] from x [S][N][N]. */
+int pfista_nudft_forward(const pfista_plan *p, const pfista_c32 *sens, const float *traj, int J,
+                         const pfista_c32 *x, pfista_c32 *kdata, hipStream_t stream);
+/* y[s] = sum_c conj(S_c) E^H kdata[s][c]: the image A^H b a Toeplitz solve takes. */
+int pfista_nudft_adjoint(const pfista_plan *p, const pfista_c32 *sens, const float *traj, int J,
+                         const pfista_c32 *kdata, pfista_c32 *y, hipStream_t stream);
 
 /* ------------------------------------------------------------ differentiation
  * Algorithm 4 unrolled for a fixed iteration count K from x_0 = z_0 = 0,

@@ -25,7 +25,7 @@ import numpy as np
 from .pfista_oracle import haar_fwd, prox_l1_haar
 
 __all__ = ["nudft_matrix", "nudft_forward", "nudft_adjoint", "nudft_normal", "toeplitz_kernel",
-           "toeplitz_normal", "nc_data_term", "pfista_nc"]
+           "toeplitz_normal", "nc_data_term", "pfista_nc", "pfista_toeplitz"]
 
 
 def nudft_matrix(traj: np.ndarray, n: int) -> np.ndarray:
@@ -114,3 +114,22 @@ def pfista_nc(sens, traj, bn, scale, lam, coef, levels, iters, history=False):
             hist.append(nc_data_term(sens, traj, bn, scale, x)
                         + lam * float(np.sum(np.abs(haar_fwd(x, levels)))))
     return x, z, hist
+
+
+def pfista_toeplitz(sens, kern, ahb, bnorm, scale, lam, coef, levels, iters):
+    """Algorithm 4 from ``A^H b`` and ``||b||`` alone (as a Toeplitz solver
+    receives its data): ``N' = scale T`` with the Toeplitz operator of ``kern``,
+    ``a = sqrt(scale) A^H b / ||b||``; the same iteration as ``pfista_nc``."""
+    a = np.sqrt(scale) * ahb / bnorm
+    x = np.zeros_like(a)
+    z = np.zeros_like(a)
+    for k in range(iters):
+        g = toeplitz_normal(sens, kern, z, scale) - a
+        h = float(coef[-1]) * g
+        for ci in reversed([float(c) for c in coef[:-1]]):
+            h = ci * g + toeplitz_normal(sens, kern, h, scale)
+        x_new = prox_l1_haar(z - h, lam, levels)
+        beta = k / (k + 3.0)
+        z = x_new + beta * (x_new - x)
+        x = x_new
+    return x

@@ -16,13 +16,14 @@ import re
 __all__ = [
     "Plan", "PfistaError", "load_library", "library_path", "poly_coefficients",
     "poly_coefficients_weighted", "poly_coefficients_chebyshev", "normal_apply", "poly_apply", "step", "forward", "adjoint", "data_term",
-    "power_iteration", "profile_normal", "solve", "MASK_2D", "MASK_1D", "header_functions",
+    "power_iteration", "profile_normal", "solve", "MASK_2D", "MASK_1D", "TOEPLITZ", "header_functions",
+    "toeplitz_kernel", "nudft_forward", "nudft_adjoint",
     "Batch", "batch_solve", "TUNE_CANDIDATES", "Unrolled", "unrolled_pfista",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-MASK_2D, MASK_1D = 0, 1
+MASK_2D, MASK_1D, TOEPLITZ = 0, 1, 2
 OK, EINVAL, UNSUPPORTED, EHIP, DIVERGED = 0, -1, -2, -3, -4
 
 
@@ -43,7 +44,8 @@ class _Params(ctypes.Structure):
                 ("coef", ctypes.POINTER(ctypes.c_double)), ("max_iter", ctypes.c_int),
                 ("check_every", ctypes.c_int), ("tol", ctypes.c_double),
                 ("f_stop", ctypes.c_double), ("eval_objective", ctypes.c_int),
-                ("k0", ctypes.c_int), ("graph_iters", ctypes.c_int), ("momentum", ctypes.c_int)]
+                ("k0", ctypes.c_int), ("graph_iters", ctypes.c_int), ("momentum", ctypes.c_int),
+                ("bnorm", ctypes.c_double)]
 
 
 class _Report(ctypes.Structure):
@@ -118,6 +120,9 @@ _SIGS = {
     "pfista_unroll_forward": (_I, [_VP, _VP, _VP, _VP, ctypes.POINTER(_UnrollParams), _VP, _VP, _VP, _VP]),
     "pfista_unroll_backward": (_I, [_VP, _VP, _VP, ctypes.POINTER(_UnrollParams), _VP, _VP,
                                     ctypes.POINTER(_D), _VP, _VP]),
+    "pfista_toeplitz_kernel": (_I, [_VP, _VP, _VP, _I, _VP, _VP]),
+    "pfista_nudft_forward": (_I, [_VP, _VP, _VP, _I, _VP, _VP, _VP]),
+    "pfista_nudft_adjoint": (_I, [_VP, _VP, _VP, _I, _VP, _VP, _VP]),
     "pfista_last_error": (ctypes.c_char_p, []),
 }
 
@@ -215,7 +220,13 @@ class Plan:
 
     @property
     def mask_numel(self):
+        if self.mask_kind == TOEPLITZ:
+            return self.slices * 4 * self.n * self.n
         return self.slices * self.n * (self.n if self.mask_kind == MASK_2D else 1)
+
+    def mask_dtype(self):
+        import torch
+        return torch.float32 if self.mask_kind == TOEPLITZ else torch.uint8
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -258,7 +269,7 @@ def poly_coefficients_chebyshev(degree: int, mu: float) -> list:
 def normal_apply(plan, sens, mask, x, y, alpha=1.0, w=None, beta=0.0, stream=None):
     c = _cplx()
     _check(load_library().pfista_normal_apply(
-        plan.handle, _ptr(sens, "sens", c, plan.n_coil), _ptr(mask, "mask", _u8(), plan.mask_numel),
+        plan.handle, _ptr(sens, "sens", c, plan.n_coil), _ptr(mask, "mask", plan.mask_dtype(), plan.mask_numel),
         _ptr(x, "x", c, plan.n_img), _ptr(y, "y", c, plan.n_img), float(alpha),
         _ptr(w, "w", c, plan.n_img, allow_none=True), float(beta), _ptr(plan.ws, "ws"), _stream(stream)))
     return y
@@ -268,7 +279,7 @@ def poly_apply(plan, sens, mask, inv_l, coef, g, out, stream=None):
     c = _cplx()
     arr = (ctypes.c_double * len(coef))(*[float(v) for v in coef])
     _check(load_library().pfista_poly_apply(
-        plan.handle, _ptr(sens, "sens", c, plan.n_coil), _ptr(mask, "mask", _u8(), plan.mask_numel),
+        plan.handle, _ptr(sens, "sens", c, plan.n_coil), _ptr(mask, "mask", plan.mask_dtype(), plan.mask_numel),
         float(inv_l), arr, len(coef) - 1, _ptr(g, "g", c, plan.n_img), _ptr(out, "out", c, plan.n_img),
         _ptr(plan.ws, "ws"), _stream(stream)))
     return out
@@ -287,7 +298,7 @@ def step(plan, z, pg, x_old, x_new, z_new, lam, beta_k, red, stream=None):
 def forward(plan, sens, mask, x, kspace, stream=None):
     c = _cplx()
     _check(load_library().pfista_forward(
-        plan.handle, _ptr(sens, "sens", c, plan.n_coil), _ptr(mask, "mask", _u8(), plan.mask_numel),
+        plan.handle, _ptr(sens, "sens", c, plan.n_coil), _ptr(mask, "mask", plan.mask_dtype(), plan.mask_numel),
         _ptr(x, "x", c, plan.n_img), _ptr(kspace, "kspace", c, plan.n_coil), _ptr(plan.ws, "ws"),
         _stream(stream)))
     return kspace
@@ -296,7 +307,7 @@ def forward(plan, sens, mask, x, kspace, stream=None):
 def adjoint(plan, sens, mask, kspace, y, alpha=1.0, stream=None):
     c = _cplx()
     _check(load_library().pfista_adjoint(
-        plan.handle, _ptr(sens, "sens", c, plan.n_coil), _ptr(mask, "mask", _u8(), plan.mask_numel),
+        plan.handle, _ptr(sens, "sens", c, plan.n_coil), _ptr(mask, "mask", plan.mask_dtype(), plan.mask_numel),
         _ptr(kspace, "kspace", c, plan.n_coil), _ptr(y, "y", c, plan.n_img), float(alpha),
         _ptr(plan.ws, "ws"), _stream(stream)))
     return y
@@ -306,7 +317,7 @@ def data_term(plan, sens, mask, b, x, inv_l, b_scale, stream=None) -> float:
     c = _cplx()
     out = ctypes.c_double()
     _check(load_library().pfista_data_term(
-        plan.handle, _ptr(sens, "sens", c, plan.n_coil), _ptr(mask, "mask", _u8(), plan.mask_numel),
+        plan.handle, _ptr(sens, "sens", c, plan.n_coil), _ptr(mask, "mask", plan.mask_dtype(), plan.mask_numel),
         _ptr(b, "b", c, plan.n_coil), _ptr(x, "x", c, plan.n_img), float(inv_l), float(b_scale),
         ctypes.byref(out), _ptr(plan.ws, "ws"), _stream(stream)))
     return out.value
@@ -316,7 +327,7 @@ def power_iteration(plan, sens, mask, iters, v=None, stream=None) -> float:
     c = _cplx()
     out = ctypes.c_double()
     _check(load_library().pfista_power_iteration(
-        plan.handle, _ptr(sens, "sens", c, plan.n_coil), _ptr(mask, "mask", _u8(), plan.mask_numel),
+        plan.handle, _ptr(sens, "sens", c, plan.n_coil), _ptr(mask, "mask", plan.mask_dtype(), plan.mask_numel),
         _ptr(v, "v", c, plan.n_img, allow_none=True), int(iters), ctypes.byref(out),
         _ptr(plan.ws, "ws"), _stream(stream)))
     return out.value
@@ -328,7 +339,7 @@ def profile_normal(plan, sens, mask, x, y, reps=50, stream=None) -> list:
     ms = (ctypes.c_float * 4)()
     npass = ctypes.c_int()
     _check(load_library().pfista_profile_normal(
-        plan.handle, _ptr(sens, "sens", c, plan.n_coil), _ptr(mask, "mask", _u8(), plan.mask_numel),
+        plan.handle, _ptr(sens, "sens", c, plan.n_coil), _ptr(mask, "mask", plan.mask_dtype(), plan.mask_numel),
         _ptr(x, "x", c, plan.n_img), _ptr(y, "y", c, plan.n_img), int(reps), ms, ctypes.byref(npass),
         _ptr(plan.ws, "ws"), _stream(stream)))
     return list(ms)[: npass.value]
@@ -336,7 +347,7 @@ def profile_normal(plan, sens, mask, x, y, reps=50, stream=None) -> list:
 
 def solve(plan, sens, mask, b, x, lam, degree=3, coef=None, max_iter=50, inv_l=0.0, power_iters=30,
           check_every=None, tol=0.0, f_stop=0.0, eval_objective=False, z=None, k0=0, graph_iters=0,
-          history=False, stream=None, raise_on_diverge=True, momentum=True):
+          history=False, stream=None, raise_on_diverge=True, momentum=True, bnorm=0.0):
     """Algorithm 4 through ``pfista_solve``; returns the report as a dict (with
     ``history`` when asked)."""
     c = _cplx()
@@ -350,12 +361,13 @@ def solve(plan, sens, mask, b, x, lam, degree=3, coef=None, max_iter=50, inv_l=0
     prm = _Params(float(lam), float(inv_l), int(power_iters), int(degree),
                   ctypes.cast(carr, ctypes.POINTER(ctypes.c_double)) if carr is not None else None,
                   int(max_iter), ce, float(tol), float(f_stop), int(bool(eval_objective or history)),
-                  int(k0), int(graph_iters), int(bool(momentum)))
+                  int(k0), int(graph_iters), int(bool(momentum)), float(bnorm))
     nh = max(1, -(-int(max_iter) // ce))
     hist = (ctypes.c_double * nh)() if history else None
     rep = _Report()
+    nb = plan.n_img if plan.mask_kind == TOEPLITZ else plan.n_coil
     rc = lib.pfista_solve(plan.handle, _ptr(sens, "sens", c, plan.n_coil),
-                          _ptr(mask, "mask", _u8(), plan.mask_numel), _ptr(b, "b", c, plan.n_coil),
+                          _ptr(mask, "mask", plan.mask_dtype(), plan.mask_numel), _ptr(b, "b", c, nb),
                           ctypes.byref(prm), _ptr(x, "x", c, plan.n_img),
                           _ptr(z, "z", c, plan.n_img, allow_none=True),
                           ctypes.cast(hist, ctypes.POINTER(ctypes.c_double)) if hist is not None else None,
@@ -492,7 +504,7 @@ class Unrolled:
             raise ValueError(f"expected {self.degree + 1} coefficients")
         prm = self._params(lam, coef)
         _check(load_library().pfista_unroll_forward(
-            pl.handle, _ptr(sens, "sens", c, pl.n_coil), _ptr(mask, "mask", _u8(), pl.mask_numel),
+            pl.handle, _ptr(sens, "sens", c, pl.n_coil), _ptr(mask, "mask", pl.mask_dtype(), pl.mask_numel),
             _ptr(b, "b", c, pl.n_coil), ctypes.byref(prm), _ptr(x, "x", c, pl.n_img), _ptr(self.ckpt, "ckpt"),
             _ptr(self.ws, "ws"), _stream(stream)))
 
@@ -502,7 +514,7 @@ class Unrolled:
         prm = self._params(lam, coef)
         g = (ctypes.c_double * (self.degree + 2))()
         _check(load_library().pfista_unroll_backward(
-            pl.handle, _ptr(sens, "sens", c, pl.n_coil), _ptr(mask, "mask", _u8(), pl.mask_numel),
+            pl.handle, _ptr(sens, "sens", c, pl.n_coil), _ptr(mask, "mask", pl.mask_dtype(), pl.mask_numel),
             ctypes.byref(prm), _ptr(x_bar, "x_bar", c, pl.n_img), _ptr(self.ckpt, "ckpt"), g,
             _ptr(self.ws, "ws"), _stream(stream)))
         return g[0], list(g)[1:]
@@ -546,3 +558,36 @@ def unrolled_pfista(lam, coef, unrolled, sens, mask, b):
     if _UNROLLED_FN is None:
         _UNROLLED_FN = _unrolled_function()
     return _UNROLLED_FN.apply(lam, coef, unrolled, sens, mask, b)
+
+
+# ------------------------------------------------------------------ non-Cartesian set-up
+
+def toeplitz_kernel(plan, traj, kern, weights=None, stream=None):
+    """Toeplitz kernel ``kern`` (float32 [S, 2n, 2n]) of the trajectories
+    ``traj`` (float32 [S, J, 2], cycles per field of view) of a Toeplitz plan."""
+    import torch
+    J = traj.shape[-2]
+    _check(load_library().pfista_toeplitz_kernel(
+        plan.handle, _ptr(traj, "traj", torch.float32, plan.slices * J * 2),
+        _ptr(weights, "weights", torch.float32, plan.slices * J, allow_none=True), int(J),
+        _ptr(kern, "kern", torch.float32, plan.mask_numel), _stream(stream)))
+
+
+def nudft_forward(plan, sens, traj, x, kdata, stream=None):
+    """``kdata`` [S, C, J] = non-uniform DFT of the coil images ``S_c x``."""
+    import torch
+    c, J = _cplx(), traj.shape[-2]
+    _check(load_library().pfista_nudft_forward(
+        plan.handle, _ptr(sens, "sens", c, plan.n_coil), _ptr(traj, "traj", torch.float32, plan.slices * J * 2),
+        int(J), _ptr(x, "x", c, plan.n_img), _ptr(kdata, "kdata", c, plan.slices * plan.coils * J),
+        _stream(stream)))
+
+
+def nudft_adjoint(plan, sens, traj, kdata, y, stream=None):
+    """``y`` [S, N, N] = ``sum_c conj(S_c) E^H kdata_c`` (A^H b of a Toeplitz solve)."""
+    import torch
+    c, J = _cplx(), traj.shape[-2]
+    _check(load_library().pfista_nudft_adjoint(
+        plan.handle, _ptr(sens, "sens", c, plan.n_coil), _ptr(traj, "traj", torch.float32, plan.slices * J * 2),
+        int(J), _ptr(kdata, "kdata", c, plan.slices * plan.coils * J), _ptr(y, "y", c, plan.n_img),
+        _stream(stream)))

@@ -546,6 +546,305 @@ __global__ __launch_bounds__(256, 2) void k_row_inv_fwd(float2 *__restrict__ t, 
 }
 
 // ---------------------------------------------------------------------------
+// Toeplitz normal operator of a non-Cartesian trajectory: for every coil image
+//   y += conj(S_c) crop_N(IDFT_M(K DFT_M(pad_M(S_c x)))),  M = 2N,
+// with the real M x M kernel K of the trajectory, in three passes over a
+// per-coil buffer t [S][C][N][M] (only the N image rows; rows N..M-1 of the
+// padded image are zero and are never stored).
+//   k_trow_fwd   t_c[y, :] = DFT_M(pad(S_c[y, :] x[y, :]))      (y < N)
+//   k_tcol       t_c[:, k] = crop_N(IDFT_M(K[:, k] DFT_M(pad t_c[:, k])))
+//   k_trow_inv   y[r, :]  = alpha sum_c conj(S_c[r, :]) crop_N(IDFT_M t_c[r, :]) + beta w
+template <int M>
+__global__ __launch_bounds__(256) void k_trow_fwd(const float2 *__restrict__ x, const float2 *__restrict__ sens,
+                                                  float2 *__restrict__ t, int C, int tasks, int *k_inc) {
+  using Gm = Geo<M>;
+  using F = typename Gm::F;
+  constexpr int N = M / 2;
+  constexpr int T = Gm::T;
+  if (k_inc && blockIdx.x == 0 && threadIdx.x == 0) *k_inc += 1;
+  __shared__ float2 s_tw[TwLayout<F>::size()];
+  __shared__ float2 s_buf[Gm::G][Gm::LDSN];
+  const int g = threadIdx.x / T, j0 = threadIdx.x % T;
+  const int task = blockIdx.x * Gm::G + g;
+  const bool valid = task < tasks;
+  const int c = valid ? task % C : 0;
+  const int sy = valid ? task / C : 0;
+  const int s = sy / N, yy = sy % N;
+  const float2 *xr = x + (size_t)sy * N;
+  const float2 *sr = sens + ((size_t)(s * C + c) * N + yy) * N;
+  float2 v[Gm::P];
+#pragma unroll
+  for (int b = 0; b < F::NB_in; ++b) {
+    const int j = j0 + b * T;
+    const bool ok = valid && lay_in_ok<F>(j);
+#pragma unroll
+    for (int r = 0; r < F::R_in; ++r) {
+      const int i = j + r * F::B_in;
+      v[b * F::R_in + r] = (ok && i < N) ? cmul(sr[i], xr[i]) : make_float2(0.f, 0.f);
+    }
+  }
+  load_tw(s_tw, Gm::TWF, TwLayout<F>::size());
+  __syncthreads();
+  fft_run<F, -1>(v, s_buf[g], j0, s_tw);
+  float2 *tr = t + ((size_t)(s * C + c) * N + yy) * M;
+#pragma unroll
+  for (int b = 0; b < F::NB_out; ++b) {
+    const int j = j0 + b * T;
+    if (valid && lay_out_ok<F>(j)) {
+#pragma unroll
+      for (int r = 0; r < F::R_out; ++r) tr[j + r * F::B_out] = v[b * F::R_out + r];
+    }
+  }
+}
+
+template <int M>
+__global__ __launch_bounds__(256, 2) void k_tcol(float2 *__restrict__ t, const float *__restrict__ kern, int C) {
+  using Gm = Geo<M>;
+  using F = typename Gm::F;
+  using I = typename Gm::I;
+  constexpr int N = M / 2;
+  constexpr int T = Gm::T;
+  __shared__ float2 s_twF[TwLayout<F>::size()];
+  __shared__ float2 s_twI[TwLayout<I>::size()];
+  __shared__ float2 s_buf[Gm::COLS * Gm::LDSN];
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  const int ci = ln % Gm::CPW, col = wv * Gm::CPW + ci, j0 = ln / Gm::CPW;
+  float2 *bufc = s_buf + wv * Gm::CPW * Gm::LDSN + ci;
+  const int kx = blockIdx.x * Gm::COLS + col;
+  const int sc = blockIdx.y;
+  const int s = sc / C;
+  const float *ks = kern + (size_t)s * M * M;
+  float2 *tc = t + (size_t)sc * N * M;
+  float2 v[Gm::P];
+#pragma unroll
+  for (int b = 0; b < F::NB_in; ++b) {
+    const int j = j0 + b * T;
+    const bool ok = lay_in_ok<F>(j);
+#pragma unroll
+    for (int r = 0; r < F::R_in; ++r) {
+      const int yy = j + r * F::B_in;
+      v[b * F::R_in + r] = (ok && yy < N) ? tc[(size_t)yy * M + kx] : make_float2(0.f, 0.f);
+    }
+  }
+  load_tw(s_twF, Gm::TWF, TwLayout<F>::size());
+  load_tw(s_twI, Gm::TWI, TwLayout<I>::size());
+  __syncthreads();
+  fft_run<F, -1, Gm::CPW>(v, bufc, j0, s_twF);
+#pragma unroll
+  for (int b = 0; b < F::NB_out; ++b) {
+    const int j = j0 + b * T;
+    const bool ok = lay_out_ok<F>(j);
+#pragma unroll
+    for (int r = 0; r < F::R_out; ++r) {
+      const int ky = j + r * F::B_out;
+      const float kv = ok ? ks[(size_t)ky * M + kx] : 0.f;
+      v[b * F::R_out + r] = cscale(v[b * F::R_out + r], kv);
+    }
+  }
+  fft_run<I, +1, Gm::CPW>(v, bufc, j0, s_twI);
+#pragma unroll
+  for (int b = 0; b < I::NB_out; ++b) {
+    const int j = j0 + b * T;
+    if (lay_out_ok<I>(j)) {
+#pragma unroll
+      for (int r = 0; r < I::R_out; ++r) {
+        const int yy = j + r * I::B_out;
+        if (yy < N) tc[(size_t)yy * M + kx] = v[b * I::R_out + r];
+      }
+    }
+  }
+}
+
+template <int M>
+__global__ __launch_bounds__(256, 2) void k_trow_inv(const float2 *__restrict__ t, const float2 *__restrict__ sens,
+                                                   float2 *__restrict__ y, const float2 *w, float alpha, float beta,
+                                                   int C, int rows, int rpw) {
+  using Gm = Geo<M>;
+  using I = typename Gm::I;
+  constexpr int N = M / 2;
+  constexpr int T = Gm::T;
+  constexpr int G = Gm::G;
+  __shared__ float2 s_tw[TwLayout<I>::size()];
+  __shared__ float2 s_buf[G][Gm::LDSN];
+  const int g = threadIdx.x / T, j0 = threadIdx.x % T;
+  const int ro = g % rpw, cg = g / rpw, cstep = G / rpw;
+  const int row = blockIdx.x * rpw + ro;
+  const bool rvalid = row < rows;
+  const int s = rvalid ? row / N : 0, yy = rvalid ? row % N : 0;
+  float2 acc[Gm::P_IN];
+#pragma unroll
+  for (int i = 0; i < Gm::P_IN; ++i) acc[i] = make_float2(0.f, 0.f);
+  const int iters = (C + cstep - 1) / cstep;
+  for (int it = 0; it < iters; ++it) {
+    const int c = cg + it * cstep;
+    const bool valid = rvalid && c < C;
+    const size_t cimg = (size_t)(s * C + (valid ? c : 0)) * N + yy;
+    const float2 *tr = t + cimg * M;
+    const float2 *sr = sens + cimg * N;
+    float2 v[Gm::P], sv[Gm::P_IN];
+#pragma unroll
+    for (int b = 0; b < I::NB_in; ++b) {
+      const int j = j0 + b * T;
+      const bool ok = valid && lay_in_ok<I>(j);
+#pragma unroll
+      for (int r = 0; r < I::R_in; ++r) v[b * I::R_in + r] = ok ? tr[j + r * I::B_in] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int b = 0; b < I::NB_out; ++b) {
+      const int j = j0 + b * T;
+      const bool ok = valid && lay_out_ok<I>(j);
+#pragma unroll
+      for (int r = 0; r < I::R_out; ++r) {
+        const int i = j + r * I::B_out;
+        sv[b * I::R_out + r] = (ok && i < N) ? sr[i] : make_float2(0.f, 0.f);
+      }
+    }
+    if (it == 0) {
+      load_tw(s_tw, Gm::TWI, TwLayout<I>::size());
+      __syncthreads();
+    }
+    fft_run<I, +1>(v, s_buf[opaque(g)], opaque(j0), s_tw);
+#pragma unroll
+    for (int i = 0; i < Gm::P_IN; ++i) acc[i] = cadd(acc[i], cmulc(v[i], sv[i]));
+  }
+  __syncthreads();
+  float2 *red = &s_buf[0][0];
+#pragma unroll
+  for (int b = 0; b < I::NB_out; ++b) {
+    const int j = j0 + b * T;
+    if (lay_out_ok<I>(j)) {
+#pragma unroll
+      for (int r = 0; r < I::R_out; ++r) {
+        const int i = j + r * I::B_out;
+        if (i < N) red[g * N + i] = acc[b * I::R_out + r];
+      }
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < rpw * N; e += blockDim.x) {
+    const int r_o = e / N, i = e % N;
+    const int rr = blockIdx.x * rpw + r_o;
+    if (rr >= rows) continue;
+    float2 sum = red[r_o * N + i];
+    for (int q = 1; q < cstep; ++q) sum = cadd(sum, red[(q * rpw + r_o) * N + i]);
+    float2 out = cscale(sum, alpha);
+    const size_t o = (size_t)rr * N + i;
+    if (w) out = cadd(out, cscale(w[o], beta));
+    y[o] = out;
+  }
+}
+
+// Kernel of the Toeplitz operator from a trajectory (cycles per field of view,
+// [S][J][2]) and optional weights [S][J]:
+//   K[ky][kx] = (1/n^2) sum_j w_j D(kx_j/n - kx/2n) D(ky_j/n - ky/2n),
+//   D(u) = sum_{m=-(n-1)}^{n-1} exp(2 pi i m u) = sin((2n-1) pi u) / sin(pi u),
+// the DFT of the difference kernel h(m) = (1/n^2) sum_j w_j exp(2 pi i k_j.m/n)
+// on the 2n grid.  FP64 throughout; one thread per (slice, ky, kx).
+__device__ __forceinline__ double dirichlet(double u, int n) {
+  const double r = u - rint(u);                  // D has period 1 in u
+  const double sr = sin(M_PI * r);
+  if (fabs(sr) < 1e-9) return (double)(2 * n - 1);   // D(0) = 2n - 1 (2n - 1 is odd)
+  return sin((2 * n - 1) * M_PI * r) / sr;
+}
+
+__global__ __launch_bounds__(256) void k_toeplitz_kernel(const float *__restrict__ traj, const float *weights,
+                                                         int J, int n, int slices, float *__restrict__ kern) {
+  const int m = 2 * n;
+  const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (size_t)slices * m * m) return;
+  const int s = (int)(idx / ((size_t)m * m));
+  const int rem = (int)(idx % ((size_t)m * m));
+  const int ky = rem / m, kx = rem % m;
+  const float *ts = traj + (size_t)s * J * 2;
+  const float *ws = weights ? weights + (size_t)s * J : nullptr;
+  double acc = 0.0;
+  for (int j = 0; j < J; ++j) {
+    const double ax = (double)ts[2 * j] / n - (double)kx / m;
+    const double ay = (double)ts[2 * j + 1] / n - (double)ky / m;
+    const double wj = ws ? (double)ws[j] : 1.0;
+    acc += wj * dirichlet(ax, n) * dirichlet(ay, n);
+  }
+  kern[idx] = (float)(acc / ((double)n * n));
+}
+
+// Direct non-uniform DFT of the coil images (data generation and A^H b are
+// set-up work, off the iteration): FP64 phases and sums.
+//   forward: kdata[s][c][j] = (1/n) sum_(y,x) S_c x [y][x] exp(-2 pi i (kx_j x + ky_j y)/n)
+//   adjoint: y[s][r]        = sum_c conj(S_c[r]) (1/n) sum_j kdata[s][c][j] exp(+2 pi i k_j.r/n)
+__global__ __launch_bounds__(256) void k_nudft_forward(const float2 *__restrict__ sens, const float2 *__restrict__ x,
+                                                       const float *__restrict__ traj, int J, int n, int C,
+                                                       int slices, float2 *__restrict__ kdata) {
+  const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (size_t)slices * C * J) return;
+  const int j = (int)(idx % J);
+  const int sc = (int)(idx / J);
+  const int s = sc / C;
+  const double kx = traj[((size_t)s * J + j) * 2], ky = traj[((size_t)s * J + j) * 2 + 1];
+  const float2 *sm = sens + (size_t)sc * n * n;
+  const float2 *xs = x + (size_t)s * n * n;
+  // exp(-2 pi i kx / n) and exp(-2 pi i ky / n): the per-pixel phase advances by rotation
+  const double wxr = cos(-2.0 * M_PI * kx / n), wxi = sin(-2.0 * M_PI * kx / n);
+  double ar = 0.0, ai = 0.0;
+  for (int yy = 0; yy < n; ++yy) {
+    double pr = cos(-2.0 * M_PI * ky * yy / n), pi_ = sin(-2.0 * M_PI * ky * yy / n);
+    double rr = 0.0, ri = 0.0;
+    for (int xx = 0; xx < n; ++xx) {
+      const float2 a = sm[(size_t)yy * n + xx], b = xs[(size_t)yy * n + xx];
+      const double ur = (double)a.x * b.x - (double)a.y * b.y, ui = (double)a.x * b.y + (double)a.y * b.x;
+      rr += ur * pr - ui * pi_;
+      ri += ur * pi_ + ui * pr;
+      const double npr = pr * wxr - pi_ * wxi;
+      pi_ = pr * wxi + pi_ * wxr;
+      pr = npr;
+    }
+    ar += rr;
+    ai += ri;
+  }
+  kdata[idx] = make_float2((float)(ar / n), (float)(ai / n));
+}
+
+__global__ __launch_bounds__(256) void k_nudft_adjoint(const float2 *__restrict__ sens,
+                                                       const float2 *__restrict__ kdata,
+                                                       const float *__restrict__ traj, int J, int n, int C,
+                                                       int slices, float2 *__restrict__ y) {
+  const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (size_t)slices * n * n) return;
+  const int s = (int)(idx / ((size_t)n * n));
+  const int r = (int)(idx % ((size_t)n * n));
+  const int yy = r / n, xx = r % n;
+  const float *ts = traj + (size_t)s * J * 2;
+  double outr = 0.0, outi = 0.0;
+  // four coils per sweep over the samples share each sample's phase factor
+  for (int c0 = 0; c0 < C; c0 += 4) {
+    double ar[4] = {0.0, 0.0, 0.0, 0.0}, ai[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < J; ++j) {
+      // phase (kx x + ky y)/n in cycles, reduced to [-1/2, 1/2] in FP64 before the sine
+      double ph = ((double)ts[2 * j] * xx + (double)ts[2 * j + 1] * yy) / n;
+      ph -= rint(ph);
+      float sn, cs;
+      sincosf((float)(2.0 * M_PI * ph), &sn, &cs);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (c0 + q < C) {
+          const float2 b = kdata[((size_t)s * C + c0 + q) * J + j];
+          ar[q] += (double)b.x * cs - (double)b.y * sn;
+          ai[q] += (double)b.x * sn + (double)b.y * cs;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (c0 + q < C) {
+        const float2 sm = sens[((size_t)s * C + c0 + q) * n * n + r];
+        outr += sm.x * ar[q] + sm.y * ai[q];
+        outi += sm.x * ai[q] - sm.y * ar[q];
+      }
+    }
+  }
+  y[idx] = make_float2((float)(outr / n), (float)(outi / n));
+}
+
+// ---------------------------------------------------------------------------
 // One-pass normal operator for a phase-encode mask (sampled rows ky, all kx):
 // F^H M F = (F_y^H M_y F_y) (x) I, so each column only needs a y transform pair.
 // Block = COLS columns of one slice, wave-private transform groups; all coils
@@ -979,6 +1278,34 @@ __global__ __launch_bounds__(256) void k_norm2(const float2 *__restrict__ v, siz
     __syncthreads();
   }
   if (threadIdx.x == 0) partials[blockIdx.x] = s[0];
+}
+
+// FP64 partial sums of Re <x, u> and Re <x, v> (grid-stride), two per block
+__global__ __launch_bounds__(256) void k_dot2(const float2 *__restrict__ x, const float2 *__restrict__ u,
+                                              const float2 *__restrict__ v, size_t n, double *__restrict__ partials) {
+  __shared__ double s[2][4];
+  double a = 0.0, b = 0.0;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+    const float2 xe = x[i], ue = u[i], ve = v[i];
+    a += (double)xe.x * ue.x + (double)xe.y * ue.y;
+    b += (double)xe.x * ve.x + (double)xe.y * ve.y;
+  }
+  a = wave_sum_d(a);
+  b = wave_sum_d(b);
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    s[0][wv] = a;
+    s[1][wv] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2)
+    partials[2 * blockIdx.x + threadIdx.x] =
+        ((s[threadIdx.x][0] + s[threadIdx.x][1]) + s[threadIdx.x][2]) + s[threadIdx.x][3];
+}
+
+// data term through the normal equations: out = dots[0] - 2 dots[1] + 1
+__global__ void k_normal_eq_data(const double *__restrict__ dots, double *__restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = dots[0] - 2.0 * dots[1] + 1.0;
 }
 
 // the solver's iteration counter, set on the stream (no host memory involved)

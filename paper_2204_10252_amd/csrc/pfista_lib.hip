@@ -62,6 +62,9 @@ bool supported_n(int n) {
   return false;
 }
 
+// the Toeplitz operator runs transforms of length 2n
+bool supported_toeplitz_n(int n) { return n <= 256 && supported_n(2 * n); }
+
 
 std::mutex g_tw_mu;
 std::vector<int> g_tw_done;
@@ -133,12 +136,14 @@ Layout layout(const pfista_desc &d) {
   const size_t N = d.n, S = d.slices, C = d.coils;
   L.n_img = S * N * N;
   L.n_coil = S * C * N * N;
+  // the Toeplitz operator's transform buffer holds N rows of length 2N per coil image
+  const size_t n_t = d.mask_kind == PFISTA_TOEPLITZ ? 2 * L.n_coil : L.n_coil;
   const size_t step_blocks = (N / 16) * (N / 16) * S;
   const size_t col_blocks = (N / 16) * S * C;
   L.n_partials = std::max<size_t>({3 * step_blocks, col_blocks, (size_t)kNormBlocks, 16});
   size_t off = 0;
   L.t = off;
-  off = align_up(off + L.n_coil * sizeof(float2));
+  off = align_up(off + n_t * sizeof(float2));
   for (int i = 0; i < 5; ++i) {
     L.img[i] = off;
     off = align_up(off + L.n_img * sizeof(float2));
@@ -207,6 +212,45 @@ Shape shape_of(const pfista_desc &d) {
   return Shape{d.slices, d.coils, d.slices * d.coils, d.haar_levels, d.mask_kind, nullptr, nullptr, d.coils, 1, 1};
 }
 
+// Toeplitz normal operator with transforms of length M = 2N (image side N);
+// `kern` is the real M x M kernel per slice.
+template <int M> struct ToeOps {
+  using Gm = pf::Geo<M>;
+  static constexpr int N = M / 2;
+
+  static int rows_per_block(const Shape &d) {
+    int rpw = 1;
+    while (rpw * 2 * d.cmin <= Gm::G) rpw *= 2;
+    return rpw;
+  }
+  static void row_fwd(const Shape &d, const float2 *x, const float2 *sens, float2 *t, hipStream_t st, int *k_inc) {
+    const int tasks = d.slices * N * d.coils;
+    pf::k_trow_fwd<M><<<(tasks + Gm::G - 1) / Gm::G, Gm::THREADS, 0, st>>>(x, sens, t, d.coils, tasks, k_inc);
+  }
+  static void col(const Shape &d, float2 *t, const float *kern, hipStream_t st) {
+    pf::k_tcol<M><<<dim3(M / Gm::COLS, d.slices * d.coils), Gm::THREADS, 0, st>>>(t, kern, d.coils);
+  }
+  static void row_inv(const Shape &d, const float2 *t, const float2 *sens, float2 *y, const float2 *w, float alpha,
+                      float beta, hipStream_t st) {
+    const int rpw = rows_per_block(d);
+    const int rows = d.slices * N;
+    pf::k_trow_inv<M><<<(rows + rpw - 1) / rpw, Gm::THREADS, 0, st>>>(
+        t, sens, y, w, (float)((double)alpha / ((double)M * M)), beta, d.coils, rows, rpw);
+  }
+  static void normal(const Shape &d, const float2 *sens, const float *kern, const float2 *x, float2 *y, float alpha,
+                     const float2 *w, float beta, float2 *t, hipStream_t st, int *k_inc) {
+    row_fwd(d, x, sens, t, st, k_inc);
+    col(d, t, kern, st);
+    row_inv(d, t, sens, y, w, alpha, beta, st);
+  }
+  static void pass(int k, const Shape &d, const float2 *sens, const float *kern, const float2 *x, float2 *y,
+                   float alpha, const float2 *w, float beta, float2 *t, hipStream_t st) {
+    if (k == 0) row_fwd(d, x, sens, t, st, nullptr);
+    else if (k == 1) col(d, t, kern, st);
+    else row_inv(d, t, sens, y, w, alpha, beta, st);
+  }
+};
+
 template <int N, int V = 0> struct Ops {
   using Gm = pf::Geo<N, V>;
 
@@ -263,7 +307,7 @@ template <int N, int V = 0> struct Ops {
   static void chain(const Shape &d, const float2 *sens, const uint8_t *mask, const float2 *x, int m,
                     const float *alpha, const float *beta, const float2 *const *w, float2 *const *y, float2 *t,
                     hipStream_t st, int *k_inc) {
-    if (d.mask_kind == PFISTA_MASK_1D || !d.fused) {
+    if (d.mask_kind != PFISTA_MASK_2D || !d.fused) {
       const float2 *src = x;
       for (int k = 0; k < m; ++k) {
         normal(d, sens, mask, src, y[k], alpha[k], w[k], beta[k], t, st, k == 0 ? k_inc : nullptr);
@@ -285,6 +329,11 @@ template <int N, int V = 0> struct Ops {
   static void normal(const Shape &d, const float2 *sens, const uint8_t *mask, const float2 *x, float2 *y,
                      float alpha, const float2 *w, float beta, float2 *t, hipStream_t st, int *k_inc = nullptr) {
     if constexpr (V == 0) {
+      if (d.mask_kind == PFISTA_TOEPLITZ) {
+        if constexpr (N <= 256)
+          ToeOps<2 * N>::normal(d, sens, reinterpret_cast<const float *>(mask), x, y, alpha, w, beta, t, st, k_inc);
+        return;
+      }
       if (d.mask_kind == PFISTA_MASK_1D) {
         using G1 = pf::Geo1D<N>;
         const dim3 grid(N / G1::COLS, d.slices);
@@ -305,10 +354,15 @@ template <int N, int V = 0> struct Ops {
   // kernel passes timed by pfista_profile_normal: the three passes of one apply
   // and the fused inverse+forward row pass of the Horner chain (2-D mask), or
   // the single phase-encode pass; `pass` launches pass k alone
-  static int passes(const Shape &d) { return d.mask_kind == PFISTA_MASK_1D ? 1 : 4; }
+  static int passes(const Shape &d) {
+    return d.mask_kind == PFISTA_MASK_1D ? 1 : d.mask_kind == PFISTA_TOEPLITZ ? 3 : 4;
+  }
   static void pass(int k, const Shape &d, const float2 *sens, const uint8_t *mask, const float2 *x, float2 *y,
                    float alpha, const float2 *w, float beta, float2 *t, hipStream_t st) {
-    if (d.mask_kind == PFISTA_MASK_1D) {
+    if (d.mask_kind == PFISTA_TOEPLITZ) {
+      if constexpr (N <= 256 && V == 0)
+        ToeOps<2 * N>::pass(k, d, sens, reinterpret_cast<const float *>(mask), x, y, alpha, w, beta, t, st);
+    } else if (d.mask_kind == PFISTA_MASK_1D) {
       normal(d, sens, mask, x, y, alpha, w, beta, t, st);
     } else if (k == 0) {
       row_fwd(d, x, sens, t, st);
@@ -554,8 +608,10 @@ int pfista_plan_create(pfista_plan **out, const pfista_desc *d) {
   if ((long long)d->slices * d->coils > 65535) return fail(PFISTA_UNSUPPORTED, "slices * coils > 65535");
   if (d->haar_levels < 1 || d->haar_levels > 4)
     return fail(PFISTA_UNSUPPORTED, "haar_levels %d outside 1..4", d->haar_levels);
-  if (d->mask_kind != PFISTA_MASK_2D && d->mask_kind != PFISTA_MASK_1D)
+  if (d->mask_kind != PFISTA_MASK_2D && d->mask_kind != PFISTA_MASK_1D && d->mask_kind != PFISTA_TOEPLITZ)
     return fail(PFISTA_EINVAL, "mask_kind %d", d->mask_kind);
+  if (d->mask_kind == PFISTA_TOEPLITZ && !supported_toeplitz_n(d->n))
+    return fail(PFISTA_UNSUPPORTED, "Toeplitz plans need n in {64,128,160,192,256} (got %d)", d->n);
   PF_TRY(ensure_twiddles());
   pfista_plan *p = new (std::nothrow) pfista_plan;
   if (!p) return fail(PFISTA_EINVAL, "out of host memory");
@@ -658,6 +714,8 @@ int pfista_step(const pfista_plan *p, const pfista_c32 *z, const pfista_c32 *pg,
 int pfista_forward(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *mask, const pfista_c32 *x,
                    pfista_c32 *kspace, void *ws, hipStream_t stream) {
   PF_TRY(check_ops(p, sens, mask, ws));
+  if (p->d.mask_kind == PFISTA_TOEPLITZ)
+    return fail(PFISTA_UNSUPPORTED, "%s: Toeplitz plans have no Cartesian k-space (use pfista_nudft_*)", "pfista_forward");
   if (p->d.slices == 0) return PFISTA_OK;
   PF_TRY(check_ptr(x, "x"));
   PF_TRY(check_ptr(kspace, "kspace"));
@@ -671,6 +729,8 @@ int pfista_forward(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *
 int pfista_adjoint(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *mask, const pfista_c32 *kspace,
                    pfista_c32 *y, float alpha, void *ws, hipStream_t stream) {
   PF_TRY(check_ops(p, sens, mask, ws));
+  if (p->d.mask_kind == PFISTA_TOEPLITZ)
+    return fail(PFISTA_UNSUPPORTED, "%s: Toeplitz plans have no Cartesian k-space (use pfista_nudft_*)", "pfista_adjoint");
   if (p->d.slices == 0) return PFISTA_OK;
   PF_TRY(check_ptr(kspace, "kspace"));
   PF_TRY(check_ptr(y, "y"));
@@ -685,6 +745,8 @@ int pfista_data_term(const pfista_plan *p, const pfista_c32 *sens, const uint8_t
                      const pfista_c32 *x, double inv_l, double b_scale, double *out, void *ws,
                      hipStream_t stream) {
   PF_TRY(check_ops(p, sens, mask, ws));
+  if (p->d.mask_kind == PFISTA_TOEPLITZ)
+    return fail(PFISTA_UNSUPPORTED, "%s: Toeplitz plans have no Cartesian k-space (use pfista_nudft_*)", "pfista_data_term");
   if (!out) return fail(PFISTA_EINVAL, "out is NULL");
   if (p->d.slices == 0) {
     *out = 0.0;
@@ -841,13 +903,22 @@ int pfista_solve(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *ma
   const size_t nbytes = L.n_img * sizeof(float2);
   if (overlaps(x, nbytes, zb, nbytes)) return fail(PFISTA_EINVAL, "x_io overlaps z_io");
 
-  // ---- setup: ||b||, L, A'^H b'
+  // ---- setup: ||b||, L, A'^H b'.  A Toeplitz plan's b is the image A^H b and
+  // its ||b|| comes in the params.
+  const bool toe = d.mask_kind == PFISTA_TOEPLITZ;
   double h[4] = {0, 0, 0, 0};
-  norm2_dev(F2(b), L.n_coil, partials, ds->misc, stream);
-  PF_TRY(launch_status("pfista_solve(norm)"));
-  PF_HIP(hipMemcpyAsync(h, ds->misc, sizeof(double), hipMemcpyDeviceToHost, stream));
-  PF_HIP(hipStreamSynchronize(stream));
-  const double bnorm = std::sqrt(h[0]);
+  double bnorm = 0.0;
+  if (toe) {
+    if (!(prm->bnorm > 0.0) || !std::isfinite(prm->bnorm))
+      return fail(PFISTA_EINVAL, "Toeplitz plans need params.bnorm = ||b|| > 0");
+    bnorm = prm->bnorm;
+  } else {
+    norm2_dev(F2(b), L.n_coil, partials, ds->misc, stream);
+    PF_TRY(launch_status("pfista_solve(norm)"));
+    PF_HIP(hipMemcpyAsync(h, ds->misc, sizeof(double), hipMemcpyDeviceToHost, stream));
+    PF_HIP(hipStreamSynchronize(stream));
+    bnorm = std::sqrt(h[0]);
+  }
   r.bnorm = bnorm;
   double inv_l = prm->inv_l;
   if (inv_l == 0.0) {
@@ -864,8 +935,11 @@ int pfista_solve(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *ma
     if (rep) *rep = r;
     return PFISTA_OK;
   }
-  PF_DISPATCH(d.n, Ops<NN>::adjoint(shape_of(d), F2(sens), mask, F2(b), ahb, (float)(std::sqrt(inv_l) / bnorm),
-                                    at<float2>(ws, L.t), stream));
+  if (toe)
+    pf::k_scale<<<blocks_for(L.n_img), 256, 0, stream>>>(F2(b), ahb, L.n_img, (float)(std::sqrt(inv_l) / bnorm));
+  else
+    PF_DISPATCH(d.n, Ops<NN>::adjoint(shape_of(d), F2(sens), mask, F2(b), ahb, (float)(std::sqrt(inv_l) / bnorm),
+                                      at<float2>(ws, L.t), stream));
   if (prm->k0 == 0) {
     pf::k_fill<<<blocks_for(L.n_img), 256, 0, stream>>>(x, L.n_img, make_float2(0.f, 0.f));
     pf::k_fill<<<blocks_for(L.n_img), 256, 0, stream>>>(zb, L.n_img, make_float2(0.f, 0.f));
@@ -928,7 +1002,14 @@ int pfista_solve(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *ma
       return lrc;
     }
     double F = NAN;
-    if (prm->eval_objective) {
+    if (prm->eval_objective && toe) {
+      // ||A'x - b'||^2 = <x, N'x> - 2 Re <x, A'^H b'> + 1 (||b'|| = 1)
+      normal_op(d, sens, mask, x, g, (float)inv_l, nullptr, 0.f, ws, stream);
+      const unsigned nb = (unsigned)std::min<size_t>(kNormBlocks, (L.n_img + 255) / 256);
+      pf::k_dot2<<<nb, 256, 0, stream>>>(x, g, ahb, L.n_img, partials);
+      reduce(partials, (int)nb, 2, ds->misc, nullptr, stream);
+      pf::k_normal_eq_data<<<1, 64, 0, stream>>>(ds->misc, ds->data);
+    } else if (prm->eval_objective) {
       PF_DISPATCH(d.n, Ops<NN>::resid(shape_of(d), F2(sens), mask, x, F2(b), std::sqrt(inv_l), 1.0 / bnorm,
                                       at<float2>(ws, L.t), partials, stream));
       int cnt = 0;
@@ -1619,6 +1700,7 @@ int pfista_unroll_forward(const pfista_plan *p, const pfista_c32 *sens, const ui
                           const pfista_unroll_params *prm, pfista_c32 *x_out, void *ckpt, void *ws,
                           hipStream_t stream) {
   PF_TRY(check_ops(p, sens, mask, ws));
+  if (p->d.mask_kind == PFISTA_TOEPLITZ) return fail(PFISTA_UNSUPPORTED, "pfista_unroll_forward: Cartesian plans only");
   std::vector<double> c;
   PF_TRY(check_unroll(prm, c));
   if (p->d.slices == 0) return PFISTA_OK;
@@ -1668,6 +1750,7 @@ int pfista_unroll_backward(const pfista_plan *p, const pfista_c32 *sens, const u
                            const pfista_unroll_params *prm, const pfista_c32 *x_bar, const void *ckpt, double *grad,
                            void *ws, hipStream_t stream) {
   PF_TRY(check_ops(p, sens, mask, ws));
+  if (p->d.mask_kind == PFISTA_TOEPLITZ) return fail(PFISTA_UNSUPPORTED, "pfista_unroll_backward: Cartesian plans only");
   std::vector<double> c;
   PF_TRY(check_unroll(prm, c));
   if (!grad) return fail(PFISTA_EINVAL, "grad is NULL");
@@ -1747,6 +1830,63 @@ int pfista_unroll_backward(const pfista_plan *p, const pfista_c32 *sens, const u
   PF_HIP(hipMemcpyAsync(grad, gdev, (size_t)(deg + 2) * sizeof(double), hipMemcpyDeviceToHost, stream));
   PF_HIP(hipStreamSynchronize(stream));
   return PFISTA_OK;
+}
+
+}  // extern "C"
+
+// ============================================================================ non-Cartesian set-up
+namespace {
+
+int check_traj(const pfista_plan *p, const float *traj, int J) {
+  PF_TRY(check_plan(p));
+  if (p->d.mask_kind != PFISTA_TOEPLITZ) return fail(PFISTA_EINVAL, "plan is not a Toeplitz plan");
+  if (J < 1) return fail(PFISTA_EINVAL, "J must be >= 1");
+  if ((long long)J * p->d.slices * p->d.coils > (1ll << 31) - 1) return fail(PFISTA_UNSUPPORTED, "too many samples");
+  return check_ptr(traj, "traj", 4);
+}
+
+unsigned grid_for(size_t n) { return (unsigned)std::max<size_t>(1, (n + 255) / 256); }
+
+}  // namespace
+
+extern "C" {
+
+int pfista_toeplitz_kernel(const pfista_plan *p, const float *traj, const float *weights, int J, float *kern,
+                           hipStream_t stream) {
+  PF_TRY(check_traj(p, traj, J));
+  if (weights) PF_TRY(check_ptr(weights, "weights", 4));
+  PF_TRY(check_ptr(kern, "kern", 4));
+  PF_TRY(ensure_twiddles());
+  const size_t total = (size_t)p->d.slices * 4 * p->d.n * p->d.n;
+  if (total == 0) return PFISTA_OK;
+  pf::k_toeplitz_kernel<<<grid_for(total), 256, 0, stream>>>(traj, weights, J, p->d.n, p->d.slices, kern);
+  return launch_status("pfista_toeplitz_kernel");
+}
+
+int pfista_nudft_forward(const pfista_plan *p, const pfista_c32 *sens, const float *traj, int J,
+                         const pfista_c32 *x, pfista_c32 *kdata, hipStream_t stream) {
+  PF_TRY(check_traj(p, traj, J));
+  PF_TRY(check_ptr(sens, "sens"));
+  PF_TRY(check_ptr(x, "x"));
+  PF_TRY(check_ptr(kdata, "kdata"));
+  const size_t total = (size_t)p->d.slices * p->d.coils * J;
+  if (total == 0) return PFISTA_OK;
+  pf::k_nudft_forward<<<grid_for(total), 256, 0, stream>>>(F2(sens), F2(x), traj, J, p->d.n, p->d.coils,
+                                                           p->d.slices, F2(kdata));
+  return launch_status("pfista_nudft_forward");
+}
+
+int pfista_nudft_adjoint(const pfista_plan *p, const pfista_c32 *sens, const float *traj, int J,
+                         const pfista_c32 *kdata, pfista_c32 *y, hipStream_t stream) {
+  PF_TRY(check_traj(p, traj, J));
+  PF_TRY(check_ptr(sens, "sens"));
+  PF_TRY(check_ptr(kdata, "kdata"));
+  PF_TRY(check_ptr(y, "y"));
+  const size_t total = (size_t)p->d.slices * p->d.n * p->d.n;
+  if (total == 0) return PFISTA_OK;
+  pf::k_nudft_adjoint<<<grid_for(total), 256, 0, stream>>>(F2(sens), F2(kdata), traj, J, p->d.n, p->d.coils,
+                                                           p->d.slices, F2(y));
+  return launch_status("pfista_nudft_adjoint");
 }
 
 }  // extern "C"

@@ -1,0 +1,218 @@
+"""GPU parity of the non-Cartesian (Toeplitz) path against the FP64 oracle.
+
+The oracle's kernel K (DFT of the difference kernel, pinned against the direct
+non-uniform DFT) is rounded to float32 and handed to the GPU apply, so the
+apply's check is independent of the GPU kernel builder, which is checked on its
+own.  Bars: apply <= 1e-5 relative (as the Cartesian apply), kernel builder
+<= 1e-6 (FP64 sums, one rounding), direct non-uniform DFTs <= 1e-5, final
+iterate <= 1e-4.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as orc
+from synth import coil_sensitivities, make_inputs, mask_variable_density, spiral_trajectory
+from tests.gpu_util import HORNER_PARTIAL_MAX, c64, rel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def toe_case(n, coils, interleaves, samples, seed, slices=1):
+    rng = np.random.default_rng(seed)
+    sens = c64(np.stack([coil_sensitivities(n, coils, rng) for _ in range(slices)]))
+    traj = np.stack([spiral_trajectory(n, interleaves, samples, 3.0, 1.5, rng)
+                     for _ in range(slices)]).astype(np.float32)
+    x = c64(rng.standard_normal((slices, n, n)) + 1j * rng.standard_normal((slices, n, n)))
+    w = c64(rng.standard_normal((slices, n, n)) + 1j * rng.standard_normal((slices, n, n)))
+    return sens, traj, x, w
+
+
+def oracle_kernel(traj, n, weights=None):
+    ks = [orc.toeplitz_kernel(traj[s].astype(np.float64), n,
+                              None if weights is None else weights[s].astype(np.float64)).real
+          for s in range(traj.shape[0])]
+    return np.stack(ks).astype(np.float32)
+
+
+def toe_plan(n, coils, slices=1, levels=4):
+    import paper_2204_10252_amd as pf
+    return pf.Plan(n, coils, slices, haar_levels=levels, mask_kind=pf.TOEPLITZ)
+
+
+@pytest.mark.parametrize("n,coils,slices", [(64, 3, 2), (128, 2, 1), (160, 3, 1), (192, 2, 1), (256, 2, 1)])
+def test_toeplitz_normal_apply(n, coils, slices):
+    import torch
+    import paper_2204_10252_amd as pf
+    sens, traj, x, w = toe_case(n, coils, 4, 150, seed=n + slices, slices=slices)
+    kern = oracle_kernel(traj, n)
+    plan = toe_plan(n, coils, slices)
+    y = torch.empty((slices, n, n), dtype=torch.complex64, device="cuda")
+    pf.normal_apply(plan, to_dev(sens), to_dev(kern), to_dev(x), y, 0.7, to_dev(w), 0.3)
+    want = 0.7 * orc.toeplitz_normal(sens.astype(np.complex128), kern.astype(np.float64),
+                                     x.astype(np.complex128)) + 0.3 * w
+    assert rel(y.cpu().numpy(), want) <= 1e-5
+
+
+@pytest.mark.parametrize("n,weighted", [(64, False), (64, True), (256, False)])
+def test_toeplitz_kernel_builder(n, weighted):
+    import torch
+    import paper_2204_10252_amd as pf
+    _, traj, _, _ = toe_case(n, 1, 4, 200, seed=7, slices=2)
+    wts = np.random.default_rng(8).uniform(0.2, 2.0, size=traj.shape[:2]).astype(np.float32) if weighted else None
+    plan = toe_plan(n, 1, 2)
+    kern = torch.empty((2, 2 * n, 2 * n), dtype=torch.float32, device="cuda")
+    pf.toeplitz_kernel(plan, to_dev(traj), kern, weights=None if wts is None else to_dev(wts))
+    want = np.stack([orc.toeplitz_kernel(traj[s].astype(np.float64), n,
+                                         None if wts is None else wts[s].astype(np.float64)).real
+                     for s in range(2)])
+    assert rel(kern.cpu().numpy(), want) <= 1e-6
+
+
+def test_nudft_forward_and_adjoint():
+    import torch
+    import paper_2204_10252_amd as pf
+    n, C = 64, 3
+    sens, traj, x, _ = toe_case(n, C, 4, 150, seed=9, slices=2)
+    plan = toe_plan(n, C, 2)
+    J = traj.shape[1]
+    kd = torch.empty((2, C, J), dtype=torch.complex64, device="cuda")
+    pf.nudft_forward(plan, to_dev(sens), to_dev(traj), to_dev(x), kd)
+    s128, t64 = sens.astype(np.complex128), traj.astype(np.float64)
+    want = orc.nudft_forward(s128, t64, x.astype(np.complex128))
+    assert rel(kd.cpu().numpy(), want) <= 1e-5
+    kin = c64(want)
+    y = torch.empty((2, n, n), dtype=torch.complex64, device="cuda")
+    pf.nudft_adjoint(plan, to_dev(sens), to_dev(traj), to_dev(kin), y)
+    assert rel(y.cpu().numpy(), orc.nudft_adjoint(s128, t64, kin.astype(np.complex128))) <= 1e-5
+
+
+def test_on_grid_trajectory_matches_the_cartesian_apply():
+    import torch
+    import paper_2204_10252_amd as pf
+    n, C = 64, 3
+    rng = np.random.default_rng(10)
+    sens = c64(coil_sensitivities(n, C, rng))[None]
+    mask = mask_variable_density(n, 3.0, 8, rng)[None]
+    ky, kx = np.nonzero(mask[0])
+    traj = np.stack([kx, ky], axis=1).astype(np.float32)[None]
+    x = c64(rng.standard_normal((1, n, n)) + 1j * rng.standard_normal((1, n, n)))
+    plan_t = toe_plan(n, C)
+    kern = torch.empty((1, 2 * n, 2 * n), dtype=torch.float32, device="cuda")
+    pf.toeplitz_kernel(plan_t, to_dev(traj), kern)
+    yt = torch.empty((1, n, n), dtype=torch.complex64, device="cuda")
+    pf.normal_apply(plan_t, to_dev(sens), kern, to_dev(x), yt)
+    plan_c = pf.Plan(n, C, 1, haar_levels=4)
+    yc = torch.empty_like(yt)
+    pf.normal_apply(plan_c, to_dev(sens), to_dev(mask), to_dev(x), yc)
+    want = orc.normal(sens.astype(np.complex128), mask, x.astype(np.complex128))
+    assert rel(yt.cpu().numpy(), want) <= 2e-5 and rel(yc.cpu().numpy(), want) <= 1e-5
+
+
+@pytest.mark.parametrize("degree", [1, 3])
+def test_toeplitz_poly_apply(degree):
+    import torch
+    import paper_2204_10252_amd as pf
+    n, C = 128, 3
+    sens, traj, x, _ = toe_case(n, C, 4, 200, seed=11)
+    kern = oracle_kernel(traj, n)
+    s128, k64 = sens.astype(np.complex128), kern.astype(np.float64)
+    v = x.astype(np.complex128)
+    for _ in range(60):
+        v = orc.toeplitz_normal(s128, k64, v)
+        lam_max = np.linalg.norm(v)
+        v /= lam_max
+    scale = 1.0 / (1.01 * lam_max)
+    coef = [float(c) for c in orc.l2_poly_coefficients(degree)]
+    plan = toe_plan(n, C)
+    out = torch.empty((1, n, n), dtype=torch.complex64, device="cuda")
+    pf.poly_apply(plan, to_dev(sens), to_dev(kern), scale, coef, to_dev(x), out)
+    want = x.astype(np.complex128) * coef[-1]
+    for ci in reversed(coef[:-1]):
+        want = ci * x + orc.toeplitz_normal(s128, k64, want, scale)
+    assert rel(out.cpu().numpy(), want) <= 1e-5 * HORNER_PARTIAL_MAX[degree]
+
+
+def test_toeplitz_solve_matches_direct_noncartesian_oracle():
+    import torch
+    import paper_2204_10252_amd as pf
+    n, C, levels, lam = 64, 4, 3, 1e-3
+    rng = np.random.default_rng(12)
+    sens = c64(coil_sensitivities(n, C, rng))[None]
+    traj = spiral_trajectory(n, 8, 150, 4.0, 1.5, rng).astype(np.float32)[None]
+    inp = make_inputs(1)
+    s128, t64 = sens.astype(np.complex128), traj.astype(np.float64)
+    J = traj.shape[1]
+    b = orc.nudft_forward(s128, t64, inp["phantom"]) + 1e-3 * (rng.standard_normal((1, C, J))
+                                                               + 1j * rng.standard_normal((1, C, J)))
+    b = c64(b).astype(np.complex128)
+    bnorm = float(np.linalg.norm(b))
+    ahb = c64(orc.nudft_adjoint(s128, t64, b))
+    kern = oracle_kernel(traj, n)
+    v = ahb.astype(np.complex128)
+    for _ in range(100):
+        v = orc.toeplitz_normal(s128, kern.astype(np.float64), v)
+        lam_max = np.linalg.norm(v)
+        v /= lam_max
+    inv_l = 1.0 / (1.01 * lam_max)
+    coef = [float(c) for c in orc.l2_poly_coefficients(3)]
+    plan = toe_plan(n, C, levels=levels)
+    x = torch.empty((1, n, n), dtype=torch.complex64, device="cuda")
+    rep = pf.solve(plan, to_dev(sens), to_dev(kern), to_dev(ahb), x, lam, coef=coef, max_iter=30, inv_l=inv_l,
+                   bnorm=bnorm, eval_objective=True)
+    xo, _, hist = orc.pfista_nc(s128, t64, b / bnorm, inv_l, lam, coef, levels, 30, history=True)
+    assert rel(x.cpu().numpy(), xo) <= 1e-4
+    # the data term through the normal equations: absolute accuracy of FP32 <x, N'x>
+    assert rep["objective"] == pytest.approx(hist[-1], rel=1e-3, abs=1e-5)
+    with pytest.raises(pf.PfistaError):
+        pf.solve(plan, to_dev(sens), to_dev(kern), to_dev(ahb), x, lam, coef=coef, max_iter=2, inv_l=inv_l)
+
+
+def test_toeplitz_rejects_cartesian_only_calls():
+    import torch
+    import paper_2204_10252_amd as pf
+    plan = toe_plan(64, 2)
+    sens = torch.zeros((1, 2, 64, 64), dtype=torch.complex64, device="cuda")
+    kern = torch.zeros((1, 128, 128), dtype=torch.float32, device="cuda")
+    x = torch.zeros((1, 64, 64), dtype=torch.complex64, device="cuda")
+    with pytest.raises(pf.PfistaError) as e:
+        pf.forward(plan, sens, kern, x, torch.zeros((1, 2, 64, 64), dtype=torch.complex64, device="cuda"))
+    assert e.value.code == pf.UNSUPPORTED
+
+
+def test_spiral_workload_full_size():
+    # 256 x 256, 12 coils, 16 interleaves x 1024 samples; noise-free data given as
+    # A^H b = T x_true and ||b||^2 = <x_true, T x_true> (no direct DFT at this size)
+    import torch
+    import paper_2204_10252_amd as pf
+    inp = make_inputs(6)
+    n, C = inp["n"], inp["coils"]
+    sens = c64(inp["sens"])
+    traj = inp["mask"].astype(np.float32)
+    s128 = sens.astype(np.complex128)
+    plan = toe_plan(n, C)
+    kern = torch.empty((1, 2 * n, 2 * n), dtype=torch.float32, device="cuda")
+    pf.toeplitz_kernel(plan, to_dev(traj), kern)
+    ko = oracle_kernel(traj, n)
+    assert rel(kern.cpu().numpy(), ko) <= 1e-6
+    k64 = ko.astype(np.float64)
+    xt = inp["phantom"].astype(np.complex128)
+    ahb = orc.toeplitz_normal(s128, k64, xt)
+    bnorm = float(np.sqrt(np.vdot(xt, ahb).real))
+    # normal apply at full size
+    y = torch.empty((1, n, n), dtype=torch.complex64, device="cuda")
+    pf.normal_apply(plan, to_dev(sens), to_dev(ko), to_dev(c64(xt)), y)
+    assert rel(y.cpu().numpy(), orc.toeplitz_normal(s128, k64, c64(xt).astype(np.complex128))) <= 1e-5
+    v = xt
+    for _ in range(30):
+        v = orc.toeplitz_normal(s128, k64, v)
+        lam_max = np.linalg.norm(v)
+        v /= lam_max
+    inv_l = 1.0 / (1.01 * lam_max)
+    coef = [float(c) for c in orc.l2_poly_coefficients(3)]
+    x = torch.empty((1, n, n), dtype=torch.complex64, device="cuda")
+    pf.solve(plan, to_dev(sens), to_dev(ko), to_dev(c64(ahb)), x, inp["lam"], coef=coef, max_iter=10,
+             inv_l=inv_l, bnorm=bnorm)
+    xo = orc.pfista_toeplitz(s128, k64, c64(ahb).astype(np.complex128), bnorm, inv_l, inp["lam"], coef,
+                             inp["levels"], 10)
+    assert rel(x.cpu().numpy(), xo) <= 1e-4

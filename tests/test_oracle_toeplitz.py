@@ -118,3 +118,24 @@ def test_spiral_trajectory_shape_and_extent():
     assert r.max() == pytest.approx(32.0) and r.min() > 0
     # denser near the centre: more samples inside half the radius than its area share
     assert np.mean(r < 16) > 0.25
+
+
+def test_toeplitz_solver_from_normal_equations_data():
+    # the Toeplitz form of the solver (A^H b, ||b||) follows the direct one
+    n = 8
+    sens, traj, x, rng = case(n=n, coils=2, J=90, seed=6)
+    b = orc.nudft_forward(sens, traj, x) + 0.01 * crandn(rng, (1, 2, 90))
+    bn = b / np.linalg.norm(b)
+    kern = orc.toeplitz_kernel(traj[0], n)[None]
+    ahb = orc.nudft_adjoint(sens, traj, b)
+    coef = [float(c) for c in orc.l2_poly_coefficients(2)]
+    v = crandn(rng, x.shape)
+    for _ in range(200):
+        v = orc.nudft_normal(sens, traj, v)
+        lam_max = np.linalg.norm(v)
+        v /= lam_max
+    scale = 1.0 / (1.01 * lam_max)
+    xd, _, _ = orc.pfista_nc(sens, traj, bn, scale, 1e-3, coef, 2, 12)
+    xt = orc.pfista_toeplitz(sens, kern, ahb, np.linalg.norm(b), scale, 1e-3, coef, 2, 12)
+    assert np.linalg.norm(xd) > 0.1
+    np.testing.assert_allclose(xt, xd, rtol=0, atol=1e-12)
