@@ -22,6 +22,8 @@ iterations (inputs resident in HBM, graph-replayed loop).  Also reported:
   solving the slices one plan at a time;
 * the differentiation workload (8 slices 192 x 192, 12 coils, 20 unrolled
   degree-4 iterations): forward and hand-written backward pass times;
+* the non-Cartesian workload (256 x 256, 12 coils, spiral): the Toeplitz
+  normal operator and a degree-3 PFISTA iteration;
 * the FP64 oracle timed on the host cores on a bounded sample (cpu_baseline).
 
 Prints one JSON line on stdout; progress goes to stderr.
@@ -375,6 +377,62 @@ def grad_benchmark(torch, pf, dev, stream, reps=5):
             "grad_lambda": grad[0], "grad_coef": grad[1]}
 
 
+def toeplitz_benchmark(torch, pf, dev, stream, iters=50, graph_iters=10):
+    """Workload 6: non-Cartesian 256 x 256, 12 coils, variable-density spiral
+    (16 interleaves x 1024 samples); Toeplitz normal operator on 512-point
+    transforms, PFISTA degree 3.  Data, A^H b and the kernel are formed on the
+    GPU by the set-up calls (direct non-uniform DFT sums)."""
+    import numpy as np
+
+    from synth import make_inputs
+    inp = make_inputs(6)
+    n, C = inp["n"], inp["coils"]
+    plan = pf.Plan(n, C, 1, haar_levels=inp["levels"], mask_kind=pf.TOEPLITZ, device=dev)
+    sens = torch.from_numpy(inp["sens"].astype(np.complex64)).to(dev)
+    traj = torch.from_numpy(inp["mask"].astype(np.float32)).to(dev)
+    J = traj.shape[1]
+    img = torch.from_numpy(inp["phantom"].astype(np.complex64)).to(dev)
+    kd = torch.empty((1, C, J), dtype=torch.complex64, device=dev)
+    t0 = time.perf_counter()
+    pf.nudft_forward(plan, sens, traj, img, kd)
+    kd += torch.from_numpy(inp["noise"].astype(np.complex64)).to(dev)
+    ahb = torch.empty((1, n, n), dtype=torch.complex64, device=dev)
+    pf.nudft_adjoint(plan, sens, traj, kd, ahb)
+    kern = torch.empty((1, 2 * n, 2 * n), dtype=torch.float32, device=dev)
+    pf.toeplitz_kernel(plan, traj, kern)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    bnorm = float(torch.linalg.vector_norm(kd).item())
+    inv_l = 1.0 / (1.01 * pf.power_iteration(plan, sens, kern, 30))
+    x = torch.empty_like(ahb)
+    y = torch.empty_like(ahb)
+    pass_ms = pf.profile_normal(plan, sens, kern, ahb, y, reps=50, stream=stream)
+    coef = pf.poly_coefficients(3)
+    dts = []
+    with torch.cuda.stream(stream):
+        for k in (10, 10 + iters):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            pf.solve(plan, sens, kern, ahb, x, inp["lam"], coef=coef, max_iter=k, inv_l=inv_l, bnorm=bnorm,
+                     check_every=k, graph_iters=graph_iters, stream=stream)
+            torch.cuda.synchronize()
+            dts.append(time.perf_counter() - t1)
+    per_iter = (dts[1] - dts[0]) / iters
+    apply_s = sum(pass_ms) * 1e-3
+    nbytes = 8 * n * n * (C + 2) + 4 * 4 * n * n
+    m = 2 * n
+    flops = C * (n * 5 * m * math.log2(m) + 2 * m * 5 * m * math.log2(m) + n * 5 * m * math.log2(m)) + 14 * C * n * n
+    return {"workload": "non-Cartesian 256x256, 12 coils, spiral 16x1024 samples, Toeplitz on 512-point transforms",
+            "passes_us": {k: round(t * 1e3, 3) for k, t in zip(("padded_rows", "kernel_columns", "crop_combine"),
+                                                                  pass_ms)},
+            "normal_apply_us": round(apply_s * 1e6, 2), "applies_per_s": round(1.0 / apply_s, 1),
+            "algorithmic_bytes_per_apply": nbytes, "hbm_gbs": round(nbytes / apply_s / 1e9, 1),
+            "alu_tflops": round(flops / apply_s / 1e12, 3),
+            "alu_frac": round(flops / apply_s / 1e12 / PEAK_FP32_NONPACKED_TFLOPS, 4),
+            "pfista_d3_ms_per_iteration": round(1e3 * per_iter, 4),
+            "setup_ms": round(1e3 * setup_s, 1)}
+
+
 def cpu_baseline(inp, degree, seconds):
     """The FP64 oracle's PFISTA iterations on the host, for a bounded time."""
     import numpy as np
@@ -411,6 +469,7 @@ def main():
     ap.add_argument("--no-slab", action="store_true", help="skip the 32-slice slab workload")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-slice uneven batch workload")
     ap.add_argument("--no-grad", action="store_true", help="skip the differentiation workload")
+    ap.add_argument("--no-toeplitz", action="store_true", help="skip the non-Cartesian workload")
     ap.add_argument("--profile-only", action="store_true",
                     help="only the per-pass kernel timing (for a matching rocprofv3 kernel-trace run)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -511,6 +570,13 @@ def main():
         grad = grad_benchmark(torch, pf, dev, stream)
         log(f"grad: {grad}")
 
+    toe = None
+    if not args.no_toeplitz:
+        log("non-Cartesian workload")
+        torch.cuda.empty_cache()
+        toe = toeplitz_benchmark(torch, pf, dev, stream, graph_iters=args.graph_iters)
+        log(f"toeplitz: {toe}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"cpu baseline ({args.cpu_seconds:.0f} s)")
@@ -538,6 +604,7 @@ def main():
         "slab": slab,
         "batch": batch,
         "grad": grad,
+        "toeplitz": toe,
     }
     print(json.dumps(out), flush=True)
 
