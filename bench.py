@@ -15,6 +15,8 @@ iterations (inputs resident in HBM, graph-replayed loop).  Also reported:
 * time to tolerance, plain FISTA vs PFISTA d = 1..5 on the same GPU: the
   relative objective error (1e-4, the headline criterion) and the paper's
   relative iterate error, each method against its own converged solution;
+  also on a worse-conditioned workload with the shape of the paper's knee
+  case (320 x 320, 8 coils, R = 7.21) and on the slab (d = 4 vs FISTA);
 * the slab workload (32 slices 384 x 384, 32 coils, phase-encode mask): the
   HBM-streaming normal operator and a degree-4 PFISTA iteration;
 * the batch workload (64 uneven slices): the batched solver's loop time with
@@ -100,11 +102,11 @@ def load_traffic(kernel_name):
         return None
 
 
-def setup_w2(torch, pf, dev):
+def setup_w2(torch, pf, dev, wid=WORKLOAD):
     import numpy as np
 
     from synth import make_inputs
-    inp = make_inputs(WORKLOAD)
+    inp = make_inputs(wid)
     n, coils = inp["n"], inp["coils"]
     plan = pf.Plan(n, coils, 1, haar_levels=inp["levels"], mask_kind=pf.MASK_2D, device=dev)
     sens = torch.from_numpy(inp["sens"].astype(np.complex64)).to(dev)
@@ -142,14 +144,16 @@ def first_stay_below(errs, tol):
 
 def time_to_tolerance(torch, pf, plan, sens, mask, b, lam, inv_l, stream, graph_iters,
                       obj_tols=(1e-4, 1e-6), it_tols=(1e-2, 1e-3), ref_applies=6000,
-                      max_hist_applies=2400):
+                      max_hist_applies=2400, degrees=(1, 2, 3, 4, 5), iterate=True, reps=5):
     """Iterations and GPU time for each method to reach each tolerance."""
     out = {}
-    methods = [("fista", [1.0])] + [(f"pfista_d{d}", pf.poly_coefficients(d)) for d in range(1, 6)]
+    methods = [("fista", [1.0])] + [(f"pfista_d{d}", pf.poly_coefficients(d)) for d in degrees]
+    if not iterate:
+        it_tols = ()
     for name, coef in methods:
         per = len(coef)
         kref = ref_applies // per
-        shp = (1, plan.n, plan.n)
+        shp = (plan.slices, plan.n, plan.n)
         xr = torch.empty(shp, dtype=torch.complex64, device=sens.device)
         rep = pf.solve(plan, sens, mask, b, xr, lam, coef=coef, max_iter=kref, inv_l=inv_l,
                        check_every=kref // 2, history=True, graph_iters=graph_iters, stream=stream)
@@ -163,7 +167,7 @@ def time_to_tolerance(torch, pf, plan, sens, mask, b, lam, inv_l, stream, graph_
         # iterate error against the converged solution, one resumed iteration at a time
         xnorm = float(torch.linalg.vector_norm(xr))
         ierr = []
-        for k in range(kmax):
+        for k in range(kmax if iterate else 0):
             pf.solve(plan, sens, mask, b, x, lam, coef=coef, max_iter=1, inv_l=inv_l, z=z, k0=k,
                      stream=stream)
             ierr.append(float(torch.linalg.vector_norm(x - xr)) / xnorm)
@@ -175,8 +179,8 @@ def time_to_tolerance(torch, pf, plan, sens, mask, b, lam, inv_l, stream, graph_
                 res = {"iters": kstar, "applies": None if kstar is None else kstar * per, "ms": None}
                 if kstar is not None:
                     ts = sorted(timed_solve(torch, pf, plan, sens, mask, b, lam, coef, kstar, inv_l, stream,
-                                            graph_iters)[0] for _ in range(5))
-                    res["ms"] = round(1e3 * ts[2], 4)
+                                            graph_iters)[0] for _ in range(reps))
+                    res["ms"] = round(1e3 * ts[len(ts) // 2], 4)
                 entry[kind][f"{tol:g}"] = res
         out[name] = entry
         log(f"time-to-tol {name}: objective {entry['objective']}, iterate {entry['iterate']}")
@@ -196,7 +200,7 @@ def time_to_tolerance(torch, pf, plan, sens, mask, b, lam, inv_l, stream, graph_
             "summary": summary, "methods": out}
 
 
-def slab_benchmark(torch, pf, dev, stream, reps=20, iters=30, graph_iters=10):
+def slab_benchmark(torch, pf, dev, stream, reps=20, iters=30, graph_iters=10, with_ttt=True):
     """Workload 3: 32 slices 384 x 384, 32 coils, phase-encode mask."""
     import numpy as np
 
@@ -234,7 +238,14 @@ def slab_benchmark(torch, pf, dev, stream, reps=20, iters=30, graph_iters=10):
     with torch.cuda.stream(stream):
         timed_solve(torch, pf, plan, sens, mask, b, w.lam, coef, 2, inv_l, stream, graph_iters)
         dt, _, _, _ = timed_solve(torch, pf, plan, sens, mask, b, w.lam, coef, iters, inv_l, stream, graph_iters)
+        ttt = None
+        if with_ttt:
+            # run to 1e-4 relative objective: plain FISTA and the degree-4 polynomial
+            ttt = time_to_tolerance(torch, pf, plan, sens, mask, b, w.lam, inv_l, stream, graph_iters,
+                                    obj_tols=(1e-4,), ref_applies=6000, max_hist_applies=1500,
+                                    degrees=(w.degree,), iterate=False, reps=3)
     return {"workload": "32 slices 384x384, 32 coils, phase-encode mask R=8", "kernel": name,
+            "time_to_tol": ttt,
             "normal_apply_us": round(t * 1e6, 2), "applies_per_s": round(1.0 / t, 2),
             "algorithmic_bytes_per_apply": nbytes, "hbm_gbs": round(nbytes / t / 1e9, 1),
             "hbm_frac": round(nbytes / t / 1e9 / PEAK_HBM_GBS, 4),
@@ -548,12 +559,23 @@ def main():
         if not args.no_ttt:
             ttt = time_to_tolerance(torch, pf, plan, sens, mask, b, lam, inv_l, stream, args.graph_iters)
 
+    ttt_knee = None
+    if not args.no_ttt:
+        # a worse-conditioned problem with the shape of the paper's knee case
+        log("time to tolerance, knee-like workload")
+        inp7, plan7, sens7, mask7, b7, inv_l7 = setup_w2(torch, pf, dev, wid=7)
+        with torch.cuda.stream(stream):
+            ttt_knee = time_to_tolerance(torch, pf, plan7, sens7, mask7, b7, inp7["lam"], inv_l7, stream,
+                                         args.graph_iters, degrees=(1, 2, 3, 4))
+        ttt_knee["workload"] = "320x320, 8 coils, Poisson-disc-like R=7.21, lambda=1.73e-4, 4-level Haar"
+        del plan7, sens7, mask7, b7
+
     slab = None
     if not args.no_slab:
         log("slab workload")
         del x, z, y
         torch.cuda.empty_cache()
-        slab = slab_benchmark(torch, pf, dev, stream, graph_iters=args.graph_iters)
+        slab = slab_benchmark(torch, pf, dev, stream, graph_iters=args.graph_iters, with_ttt=not args.no_ttt)
         log(f"slab: {slab}")
 
     batch = None
@@ -601,6 +623,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "time_to_tol": ttt,
+        "time_to_tol_knee_like": ttt_knee,
         "slab": slab,
         "batch": batch,
         "grad": grad,

@@ -52,6 +52,8 @@ WORKLOADS = {
                  "accel_range": (3.0, 8.0), "lam_range": (2e-4, 2e-3)}),
     5: Workload(5, "batch of 8 slices 192x192, 12 coils", 192, 12, 8, "vd", 5.0, 24,
                 5e-3, 4, 5e-4, 4, 20),
+    7: Workload(7, "knee-like Cartesian SENSE 320x320, 8 coils", 320, 8, 1, "poisson", 7.21, 24,
+                5e-3, 4, 1.73e-4, 3, 200),
     6: Workload(6, "non-Cartesian 256x256, 12 coils, variable-density spiral", 256, 12, 1, "spiral",
                 None, None, 5e-3, 4, 5e-4, 3, 200,
                 {"interleaves": 16, "samples": 1024, "turns": 8.0, "power": 1.5}),
