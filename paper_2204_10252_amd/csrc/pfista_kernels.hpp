@@ -856,6 +856,9 @@ __global__ __launch_bounds__(256) void k_nudft_adjoint(const float2 *__restrict_
 // PF_1D_HOIST: let the compiler keep the per-lane index math of the transforms
 // in registers across the coil loop (a few spilled registers cost less than
 // recomputing it for every coil)
+#ifndef PF_1D_BUFLOAD
+#define PF_1D_BUFLOAD 1
+#endif
 #ifndef PF_1D_HOIST
 #define PF_1D_HOIST 1
 #endif
@@ -881,6 +884,12 @@ __global__ __launch_bounds__(Geo1D<N>::THREADS, PF_1D_WAVES) void k_normal_1d(co
   const uint8_t *mask_s = mask + (size_t)s * N;
   const float2 *xs = x + (size_t)s * N * N;
   const float2 *ss = sens + (size_t)s * C * N * N;
+#if PF_1D_BUFLOAD
+  // buffer resource over this slice's coil maps (raw, byte-addressed; reads past
+  // the end return zero)
+  const __amdgpu_buffer_rsrc_t srsrc = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float2 *>(ss), (short)0, C * N * N * (int)sizeof(float2), 0x00020000);
+#endif
   // positions yy = j + r * F::B_in (F input layout == I output layout)
   auto pos = [&](int i) { return (j0 + (i / F::R_in) * T + (i % F::R_in) * F::B_in) * N + kx; };
   auto okp = [&](int i) { return lay_in_ok<F>(j0 + (i / F::R_in) * T); };
@@ -922,6 +931,18 @@ __global__ __launch_bounds__(Geo1D<N>::THREADS, PF_1D_WAVES) void k_normal_1d(co
 #pragma unroll
     for (int i = 0; i < PI; ++i) acc[i] = cadd(acc[i], cmulc(v[i], sc[i]));
     if (c + 1 < C) {
+#if PF_1D_BUFLOAD
+      // the next coil map through buffer loads: the per-lane byte offsets are the
+      // same for every coil and the coil's offset is a scalar, so the loop does no
+      // 64-bit address arithmetic per load
+      const int soff = (c + 1) * N * N * (int)sizeof(float2);
+#pragma unroll
+      for (int i = 0; i < PI; ++i) {
+        const unsigned o = (unsigned)((j0 + (i / F::R_in) * T + (i % F::R_in) * F::B_in) * N + kx) * 8u;
+        sc[i] = okp(i) ? __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(srsrc, o, soff, 0))
+                       : make_float2(0.f, 0.f);
+      }
+#else
       const float2 *snp = ss + (size_t)(c + 1) * N * N;
       const int kxl = PF_1D_HOIST ? kx : opaque(kx);
 #pragma unroll
@@ -929,6 +950,7 @@ __global__ __launch_bounds__(Geo1D<N>::THREADS, PF_1D_WAVES) void k_normal_1d(co
         const int o = (jl + (i / F::R_in) * T + (i % F::R_in) * F::B_in) * N + kxl;
         sc[i] = okp(i) ? snp[o] : make_float2(0.f, 0.f);
       }
+#endif
     }
   }
   float2 *ys = y + (size_t)s * N * N;
