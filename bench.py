@@ -76,11 +76,11 @@ def pass_model(n, coils, slices, kind, degree):
     ]
 
 
-def load_traffic(kernel_name):
+def load_traffic(kernel_name, fname="traffic_column_pass_256x16.txt"):
     """HBM traffic per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel sources (else None)."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "traffic_column_pass_256x16.txt")
+    path = os.path.join(ROOT, "profiles", fname)
     if not os.path.exists(path):
         return None
     src = os.path.join(ROOT, "paper_2204_10252_amd", "csrc")
@@ -262,8 +262,11 @@ def slab_benchmark(torch, pf, dev, stream, reps=20, iters=30, graph_iters=10, wi
             ttt = time_to_tolerance(torch, pf, plan, sens, mask, b, w.lam, inv_l, stream, graph_iters,
                                     obj_tols=(1e-4,), ref_applies=6000, max_hist_applies=1500,
                                     degrees=(w.degree,), iterate=False, reps=3)
+    traffic = load_traffic(name, "traffic_phase_encode_384x32_slab.txt")
     return {"workload": "32 slices 384x384, 32 coils, phase-encode mask R=8", "kernel": name,
-            "time_to_tol": ttt,
+            "time_to_tol": ttt, "traffic": traffic,
+            "hbm_gbs_measured": None if traffic is None else round(traffic / t / 1e9, 1),
+            "hbm_frac_measured": None if traffic is None else round(traffic / t / 1e9 / PEAK_HBM_GBS, 4),
             "normal_apply_us": round(t * 1e6, 2), "applies_per_s": round(1.0 / t, 2),
             "algorithmic_bytes_per_apply": nbytes, "hbm_gbs": round(nbytes / t / 1e9, 1),
             "hbm_frac": round(nbytes / t / 1e9 / PEAK_HBM_GBS, 4),

@@ -123,6 +123,10 @@ struct DevState {
   double misc[4];
 };
 
+// the solver's iteration counter, set on the stream by a kernel (no host
+// memory is read after the call returns); the next chain advances it by one
+void set_counter(DevState *ds, int k, hipStream_t st) { pf::k_set_counter<<<1, 64, 0, st>>>(&ds->k, k); }
+
 constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -832,7 +836,10 @@ int pfista_profile_normal(const pfista_plan *p, const pfista_c32 *sens, const ui
   float2 *t = at<float2>(ws, L.t);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   PF_HIP(hipEventCreate(&e0));
-  PF_HIP(hipEventCreate(&e1));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(PFISTA_EHIP, "pfista_profile_normal: event create failed");
+  }
   int rc = PFISTA_OK;
   // each pass `reps` times back to back (every pass leaves valid inputs for the
   // next: the column pass is a projection, the row passes recompute their outputs)
@@ -945,8 +952,7 @@ int pfista_solve(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *ma
     pf::k_fill<<<blocks_for(L.n_img), 256, 0, stream>>>(zb, L.n_img, make_float2(0.f, 0.f));
   }
   const int k0 = prm->k0;
-  const int k_start = k0 - 1;   // the first gradient apply advances it to k0
-  PF_HIP(hipMemcpyAsync(&ds->k, &k_start, sizeof(int), hipMemcpyHostToDevice, stream));
+  set_counter(ds, k0 - 1, stream);   // the first gradient apply advances it to k0
   PF_TRY(launch_status("pfista_solve(setup)"));
 
   const int deg = (int)c.size() - 1;
@@ -1213,7 +1219,7 @@ struct BatchRun {
   ~BatchRun() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     for (size_t i = 1; i < br.size(); ++i)
-      if (br[i]) (void)hipStreamDestroy(br[i]);
+      if (br[i] && br[i] != br[0]) (void)hipStreamDestroy(br[i]);
     for (hipEvent_t e : join)
       if (e) (void)hipEventDestroy(e);
     if (fork) (void)hipEventDestroy(fork);
@@ -1398,7 +1404,6 @@ int pfista_batch_solve(const pfista_batch *b, const pfista_c32 *const *sens, con
   for (int s = 0; s < count; ++s) bn[s] = std::sqrt(bn[s]);
 
   std::vector<std::vector<float>> lam_h(ng);
-  const int k_init = -1;   // the first gradient apply advances it to 0
   for (int gi = 0; gi < ng; ++gi) {
     const BGroup &G = b->g[gi];
     const size_t nn = (size_t)G.n * G.n;
@@ -1423,9 +1428,11 @@ int pfista_batch_solve(const pfista_batch *b, const pfista_c32 *const *sens, con
                                                at<float2>(ws, G.o_t), stream));
     pf::k_fill<<<blocks_for(G.n_img()), 256, 0, stream>>>(at<float2>(ws, G.o_img[3]), G.n_img(), make_float2(0.f, 0.f));
     pf::k_fill<<<blocks_for(G.n_img()), 256, 0, stream>>>(at<float2>(ws, G.o_img[4]), G.n_img(), make_float2(0.f, 0.f));
-    PF_HIP(hipMemcpyAsync(&at<DevState>(ws, G.o_state)->k, &k_init, sizeof(int), hipMemcpyHostToDevice, stream));
+    set_counter(at<DevState>(ws, G.o_state), -1, stream);   // the first gradient apply advances it to 0
   }
   PF_TRY(launch_status("pfista_batch_solve(setup)"));
+  // the per-group tables were copied from host vectors: let the copies land
+  PF_HIP(hipStreamSynchronize(stream));
 
   // ---- launch shape per group
   std::vector<int> cand(ng, 0);
@@ -1447,7 +1454,8 @@ int pfista_batch_solve(const pfista_batch *b, const pfista_c32 *const *sens, con
   // ---- branches: groups spread by longest-processing-time on coil-image pixels
   BatchRun run;
   const int nb = std::min(prm->streams, ng);
-  run.br.assign(nb, stream);
+  run.br.assign(nb, nullptr);   // slots 1.. are owned and destroyed by BatchRun
+  run.br[0] = stream;
   std::vector<int> branch(ng, 0);
   if (nb > 1) {
     for (int i = 1; i < nb; ++i) PF_HIP(hipStreamCreateWithFlags(&run.br[i], hipStreamNonBlocking));
@@ -1658,8 +1666,6 @@ size_t ckpt_bytes(const pfista_desc &d, const ULayout &U) {
   return (size_t)(1 + 2 * U.nck) * layout(d).n_img * sizeof(float2);
 }
 
-// the iteration counter the step kernel reads: the next chain advances it by one
-void set_counter(DevState *ds, int k, hipStream_t st) { pf::k_set_counter<<<1, 64, 0, st>>>(&ds->k, k); }
 
 // One forward step of Algorithm 4 from (x, z): writes g and pg, then x, z.
 void unroll_step(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *mask, const std::vector<double> &c,
