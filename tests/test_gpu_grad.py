@@ -75,6 +75,26 @@ def test_gradient_matches_oracle(w1, degree, momentum):
     close(got, want)
 
 
+@pytest.mark.parametrize("levels", [1, 2, 4])
+def test_gradient_every_haar_depth(w1, levels):
+    # the pull-back's level recursion at every supported depth (W1 itself uses 3)
+    import torch
+    inp, sens, s128, b, bn, inv_l = w1
+    inp = dict(inp, levels=levels)
+    K, lam, coef = 8, inp["lam"], coefs(2)
+    u = gpu_unrolled(inp, 2, K, inv_l)
+    ts, tm, tb = to_dev(sens), to_dev(inp["mask"]), to_dev(b)
+    x = torch.empty((1, 64, 64), dtype=torch.complex64, device="cuda")
+    u.forward(ts, tm, tb, x, lam, coef)
+    xo, _ = orc.unrolled_forward(s128, inp["mask"], bn, inv_l, lam, coef, levels, K)
+    assert rel(x.cpu().numpy(), xo) <= 1e-4
+    rng = np.random.default_rng(20 + levels)
+    xbar = c64(rng.standard_normal(xo.shape) + 1j * rng.standard_normal(xo.shape))
+    gl, gc = u.backward(ts, tm, to_dev(xbar), lam, coef)
+    ol, oc = orc.unrolled_vjp(s128, inp["mask"], bn, inv_l, lam, coef, levels, K, xbar.astype(np.complex128))
+    close(np.concatenate([[gl], gc]), np.concatenate([[ol], oc]))
+
+
 def test_checkpoint_interval_does_not_change_the_gradient(w1):
     import torch
     inp, sens, s128, b, bn, inv_l = w1
