@@ -569,14 +569,26 @@ def main():
         name, flops, nbytes, nl = model[k]
         t_k = pass_ms[k] * 1e-3
         achieved_tf = flops / t_k / 1e12
+        achieved_gbs = nbytes / t_k / 1e9
         traffic = load_traffic(name)
-        roofline = {"bound": "alu", "kernel": name, "achieved": round(achieved_tf, 3),
-                    "peak": round(PEAK_FP32_NONPACKED_TFLOPS, 1), "unit": "TFLOP/s",
-                    "frac": round(achieved_tf / PEAK_FP32_NONPACKED_TFLOPS, 4), "traffic": traffic,
-                    "launches_per_iteration": nl, "avg_launch_us": round(pass_ms[k] * 1e3, 3),
-                    "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": nbytes,
-                    "hbm_frac": round(nbytes / t_k / 1e9 / PEAK_HBM_GBS, 4),
-                    "passes_us": {m[0]: round(t * 1e3, 3) for m, t in zip(model, pass_ms)}}
+        # the kernel's bound from its arithmetic intensity against the ridge point
+        ridge = PEAK_FP32_NONPACKED_TFLOPS * 1e3 / PEAK_HBM_GBS          # flop per byte
+        intensity = flops / nbytes
+        if intensity < ridge:
+            roofline = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": PEAK_HBM_GBS,
+                        "unit": "GB/s", "frac": round(achieved_gbs / PEAK_HBM_GBS, 4),
+                        "alu_frac": round(achieved_tf / PEAK_FP32_NONPACKED_TFLOPS, 4)}
+        else:
+            roofline = {"bound": "alu", "achieved": round(achieved_tf, 3),
+                        "peak": round(PEAK_FP32_NONPACKED_TFLOPS, 1), "unit": "TFLOP/s",
+                        "frac": round(achieved_tf / PEAK_FP32_NONPACKED_TFLOPS, 4),
+                        "hbm_frac": round(achieved_gbs / PEAK_HBM_GBS, 4)}
+        roofline.update({"traffic": traffic, "kernel": name, "intensity_flop_per_byte": round(intensity, 2),
+                         "ridge_flop_per_byte": round(ridge, 2),
+                         "traffic_gbs": None if traffic is None else round(traffic / t_k / 1e9, 1),
+                         "launches_per_iteration": nl, "avg_launch_us": round(pass_ms[k] * 1e3, 3),
+                         "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": nbytes,
+                         "passes_us": {m[0]: round(t * 1e3, 3) for m, t in zip(model, pass_ms)}})
         apply_us = sum(pass_ms[:3]) * 1e3
         roofline["normal_apply_us"] = round(apply_us, 3)
         log(f"passes (us): {roofline['passes_us']}")
