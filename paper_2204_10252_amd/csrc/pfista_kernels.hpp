@@ -14,6 +14,13 @@
 //   k_row_inv   y[r, :]  = alpha sum_c conj(S_c[r, :]) IDFT_x t_c[r, :] + beta w
 // For a phase-encode mask the x-transform pair cancels (F_x^H F_x = I) and one
 // pass does everything: k_normal_1d.
+//
+// Also here: the Toeplitz operator of a non-Cartesian trajectory (k_trow_fwd,
+// k_tcol, k_trow_inv on 2N-point transforms, and the set-up kernels that build
+// its kernel and the direct non-uniform DFTs); the fused FISTA step (k_step) and
+// its pull-back for differentiation (k_prox_vjp, k_poly_combine_dot); FP64
+// reductions, per slice for batches (k_reduce_seg).  Batch groups whose slices
+// have different coil counts pass the cb / cs coil-image tables described below.
 
 #pragma once
 #include "pfista_fft.hpp"
