@@ -168,14 +168,15 @@ template <class PL> __device__ __forceinline__ bool lay_out_ok(int j) {
 // coil ci - cb[s] of slice s = cs[ci].  cb == nullptr means every slice has C
 // coils (ci = s * C + c); otherwise slice s owns images cb[s] .. cb[s+1]-1.
 
-// Pass 1: t_c[s, y, :] = DFT_x(S_c[s, y, :] * x[s, y, :]).  Uniform coil count:
-// task = (s, y, c), c fastest; per-slice coil counts: task = (ci, y).
+// Pass 1: t_c[s, y, :] = DFT_x(S_c[s, y, :] * x[s, y, :]); task = (s, y, c), c
+// fastest, so the transform groups of a block share rows of x.  With per-slice
+// coil counts slice s owns tasks cb[s]*N .. cb[s+1]*N - 1.
 // A transform group is T consecutive lanes of one wave (wave-level hand-over).
 template <int N, int V = 0>
 __global__ __launch_bounds__(256) void k_row_fwd(const float2 *__restrict__ x,
                                                  const float2 *__restrict__ sens,
                                                  float2 *__restrict__ t, int C, int tasks,
-                                                 int *k_inc, const int *__restrict__ cs) {
+                                                 int *k_inc, const int *__restrict__ cb, int slices) {
   using Gm = Geo<N, V>;
   using F = typename Gm::F;
   // the solver's iteration counter: advanced here, read by the step kernel of
@@ -188,10 +189,19 @@ __global__ __launch_bounds__(256) void k_row_fwd(const float2 *__restrict__ x,
   const int task = blockIdx.x * Gm::G + g;
   const bool valid = task < tasks;
   int s, yy, cim;
-  if (cs) {
-    cim = valid ? task / N : 0;
-    yy = valid ? task % N : 0;
-    s = cs[cim];
+  if (cb) {
+    const int tk = valid ? task : 0;
+    int lo = 0, hi = slices - 1;   // the slice whose task range holds tk
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (cb[mid] * N <= tk) lo = mid;
+      else hi = mid - 1;
+    }
+    s = lo;
+    const int base = cb[s], cnum = cb[s + 1] - base;
+    const int local = tk - base * N;
+    yy = local / cnum;
+    cim = base + local % cnum;
   } else {
     const int c = valid ? task % C : 0;
     const int sy = valid ? task / C : 0;

@@ -262,7 +262,7 @@ template <int N, int V = 0> struct Ops {
                       int *k_inc = nullptr) {
     const int tasks = d.images * N;
     const int grid = (tasks + Gm::G - 1) / Gm::G;
-    pf::k_row_fwd<N, V><<<grid, Gm::THREADS, 0, st>>>(x, sens, t, d.coils, tasks, k_inc, d.cs);
+    pf::k_row_fwd<N, V><<<grid, Gm::THREADS, 0, st>>>(x, sens, t, d.coils, tasks, k_inc, d.cb, d.slices);
   }
 
   template <int MODE>
