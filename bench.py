@@ -142,9 +142,35 @@ def first_stay_below(errs, tol):
     return None
 
 
+def cold_warm_apply(torch, pf, plan, sens, mask, x, y, stream, reps=20, flush_mb=512):
+    """One normal apply timed alone with HIP events: cold (a 512 MB buffer is
+    written first, which evicts the 256 MB Infinity Cache) and warm (right after
+    another apply).  Medians over `reps`."""
+    flush = torch.empty(flush_mb * 2**20 // 4, dtype=torch.float32, device=sens.device)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    cold, warm = [], []
+    with torch.cuda.stream(stream):
+        for _ in range(reps):
+            flush.fill_(1.0)
+            e0.record(stream)
+            pf.normal_apply(plan, sens, mask, x, y, 1.0, stream=stream)
+            e1.record(stream)
+            e1.synchronize()
+            cold.append(e0.elapsed_time(e1))
+            e0.record(stream)
+            pf.normal_apply(plan, sens, mask, x, y, 1.0, stream=stream)
+            e1.record(stream)
+            e1.synchronize()
+            warm.append(e0.elapsed_time(e1))
+    del flush
+    c, w = sorted(cold)[reps // 2] * 1e3, sorted(warm)[reps // 2] * 1e3
+    return {"cold_apply_us": round(c, 2), "warm_apply_us": round(w, 2),
+            "cold_applies_per_s": round(1e6 / c, 1), "warm_applies_per_s": round(1e6 / w, 1)}
+
+
 def time_to_tolerance(torch, pf, plan, sens, mask, b, lam, inv_l, stream, graph_iters,
                       obj_tols=(1e-4, 1e-6), it_tols=(1e-2, 1e-3), ref_applies=6000,
-                      max_hist_applies=2400, degrees=(1, 2, 3, 4, 5), iterate=True, reps=5):
+                      max_hist_applies=2400, degrees=(1, 2, 3, 4, 5), iterate=True, reps=11):
     """Iterations and GPU time for each method to reach each tolerance."""
     out = {}
     methods = [("fista", [1.0])] + [(f"pfista_d{d}", pf.poly_coefficients(d)) for d in degrees]
@@ -465,6 +491,38 @@ def toeplitz_benchmark(torch, pf, dev, stream, iters=50, graph_iters=10):
             "setup_ms": round(1e3 * setup_s, 1)}
 
 
+def cpu_oracle_applies(seconds_each=1.0):
+    """The FP64 oracle's normal apply at each workload's per-slice shape, on one
+    thread and with scipy.fft using every available core (the oracle's code is
+    unchanged; only scipy's worker count differs)."""
+    import numpy as np
+    import scipy.fft
+
+    import oracle as orc
+    from synth import make_slice_inputs
+    try:
+        ncores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncores = os.cpu_count() or 1
+    out = {"cores_all": ncores}
+    for wid, label in ((1, "64x64x4"), (2, "256x256x16"), (5, "192x192x12"), (3, "384x384x32_phase_encode")):
+        inp = make_slice_inputs(wid, 0)
+        sens = inp["sens"][None]
+        mask = inp["mask"][None]
+        x = inp["phantom"][None]
+        res = {}
+        for key, workers in (("one_thread_ms", 1), ("all_cores_ms", ncores)):
+            with scipy.fft.set_workers(workers):
+                orc.normal(sens, mask, x)
+                k, t0 = 0, time.perf_counter()
+                while time.perf_counter() - t0 < seconds_each:
+                    orc.normal(sens, mask, x)
+                    k += 1
+                res[key] = round(1e3 * (time.perf_counter() - t0) / k, 3)
+        out[label] = res
+    return out
+
+
 def cpu_baseline(inp, degree, seconds):
     """The FP64 oracle's PFISTA iterations on the host, for a bounded time."""
     import numpy as np
@@ -592,6 +650,8 @@ def main():
         apply_us = sum(pass_ms[:3]) * 1e3
         roofline["normal_apply_us"] = round(apply_us, 3)
         log(f"passes (us): {roofline['passes_us']}")
+        cold = cold_warm_apply(torch, pf, plan, sens, mask, x, y, stream)
+        log(f"apply cold/warm (us): {cold}")
 
         ttt = None
         if not args.no_ttt:
@@ -638,9 +698,12 @@ def main():
         log(f"toeplitz: {toe}")
 
     cpu = None
+    cpu_applies = None
     if not args.no_cpu_baseline:
         log(f"cpu baseline ({args.cpu_seconds:.0f} s)")
         cpu = cpu_baseline(inp, d, args.cpu_seconds)
+        cpu_applies = cpu_oracle_applies()
+        log(f"oracle applies: {cpu_applies}")
 
     out = {
         "metric": "A^H A applies/s (256^2, 16 coils); time to 1e-4 rel. objective vs plain FISTA",
@@ -659,7 +722,9 @@ def main():
                    "degree": d, "step": f"1 PFISTA iteration = {d + 1} A^H A applies + prox/momentum",
                    "graph_iters": args.graph_iters},
         "roofline": roofline,
+        "apply_cold_warm": cold,
         "cpu_baseline": cpu,
+        "cpu_oracle_apply_ms": cpu_applies,
         "time_to_tol": ttt,
         "time_to_tol_knee_like": ttt_knee,
         "slab": slab,
