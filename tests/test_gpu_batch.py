@@ -207,3 +207,27 @@ def test_uneven_workload_full_size_sampled():
         print(f"slice {i} ({prep[i]['n']}x{prep[i]['coils']}): rel {rel(xs[i][None], xo):.2e}", flush=True)
         assert rel(xs[i][None], xo) <= 1e-4
         assert rep["slices"][i]["objective"] == pytest.approx(hist[-1], rel=1e-5)
+
+
+def test_batch_extremes():
+    # a 512 x 512 single-coil slice, a one-level slice, and a batch of one slice
+    coef = [float(v) for v in orc.l2_poly_coefficients(2)]
+    sl = [prepare(custom_slice(512, 1, 4, 5e-4, 31), inv_l=1.0), prepare(custom_slice(64, 2, 1, 1e-3, 32))]
+    xs, rep = run_batch(sl, coef, 6, tune=-1)
+    for x, p in zip(xs, sl):
+        xo, _, _ = oracle_run(p, coef, 6)
+        assert rel(x[None], xo) <= 1e-4
+    xs, _ = run_batch(sl[1:], coef, 6)
+    xo, _, _ = oracle_run(sl[1], coef, 6)
+    assert rel(xs[0][None], xo) <= 1e-4
+
+
+def test_batch_zero_data_slice():
+    # a slice with b = 0 stays at x = 0 (its normalisation factor is 0) next to a normal one
+    coef = [float(v) for v in orc.l2_poly_coefficients(2)]
+    p = prepare(custom_slice(64, 3, 3, 1e-3, 33))
+    z = dict(p, b=np.zeros_like(p["b"]))
+    xs, rep = run_batch([p, z], coef, 8)
+    xo, _, _ = oracle_run(p, coef, 8)
+    assert rel(xs[0][None], xo) <= 1e-4
+    assert np.all(xs[1] == 0) and rep["slices"][1]["bnorm"] == 0.0

@@ -216,3 +216,36 @@ def test_spiral_workload_full_size():
     xo = orc.pfista_toeplitz(s128, k64, c64(ahb).astype(np.complex128), bnorm, inv_l, inp["lam"], coef,
                              inp["levels"], 10)
     assert rel(x.cpu().numpy(), xo) <= 1e-4
+
+
+def test_toeplitz_multislice_solve_and_unroll_rejection():
+    import torch
+    import paper_2204_10252_amd as pf
+    n, C, S, levels, lam = 64, 3, 2, 2, 1e-3
+    sens, traj, x0, _ = toe_case(n, C, 6, 120, seed=14, slices=S)
+    s128, t64 = sens.astype(np.complex128), traj.astype(np.float64)
+    rng = np.random.default_rng(15)
+    J = traj.shape[1]
+    b = c64(orc.nudft_forward(s128, t64, x0.astype(np.complex128))
+            + 1e-2 * (rng.standard_normal((S, C, J)) + 1j * rng.standard_normal((S, C, J)))).astype(np.complex128)
+    bnorm = float(np.linalg.norm(b))
+    ahb = c64(orc.nudft_adjoint(s128, t64, b))
+    kern = oracle_kernel(traj, n)
+    v = ahb.astype(np.complex128)
+    for _ in range(100):
+        v = orc.toeplitz_normal(s128, kern.astype(np.float64), v)
+        lam_max = np.linalg.norm(v)
+        v /= lam_max
+    inv_l = 1.0 / (1.01 * lam_max)
+    coef = [float(c) for c in orc.l2_poly_coefficients(2)]
+    plan = toe_plan(n, C, S, levels=levels)
+    x = torch.empty((S, n, n), dtype=torch.complex64, device="cuda")
+    pf.solve(plan, to_dev(sens), to_dev(kern), to_dev(ahb), x, lam, coef=coef, max_iter=15, inv_l=inv_l,
+             bnorm=bnorm)
+    xo, _, _ = orc.pfista_nc(s128, t64, b / bnorm, inv_l, lam, coef, levels, 15)
+    assert rel(x.cpu().numpy(), xo) <= 1e-4
+    u = pf.Unrolled(plan, 2, 4, inv_l)
+    kspace_shaped = torch.zeros((S, C, n, n), dtype=torch.complex64, device="cuda")
+    with pytest.raises(pf.PfistaError) as e:
+        u.forward(to_dev(sens), to_dev(kern), kspace_shaped, x, lam, coef)
+    assert e.value.code == pf.UNSUPPORTED
