@@ -178,6 +178,14 @@ int pfista_poly_coefficients_weighted(int degree, double alpha, double *coef);
  * HOST coef[0..degree], ascending powers.  0 <= degree <= 8. */
 int pfista_poly_coefficients_chebyshev(int degree, double mu, double *coef);
 
+/* Launch-shape candidates of the normal-operator chain (2-D masks), which a
+ * solve (pfista_params.tune) or a batch group (pfista_batch_params.tune) can be
+ * forced to with tune = k + 1: candidate k uses radix schedule k % 2 (0:
+ * default, 1: twice the lanes per transform), fuses the Horner row passes
+ * unless (k / 2) % 2, and multiplies the rows per coil-combine block by
+ * 2^(k / 4).  Every candidate computes the same operator. */
+#define PFISTA_TUNE_CANDIDATES 12
+
 typedef struct {
   double lambda;       /* l1 weight in normalised units */
   double inv_l;        /* 1/L > 0; 0: estimate L = 1.01 * power iteration */
@@ -198,6 +206,11 @@ typedef struct {
   double bnorm;        /* Toeplitz plans: ||b|| of the non-Cartesian data (> 0);
                           their `b` argument is the image A^H b [S][N][N].
                           Ignored by Cartesian plans (they compute ||b||). */
+  int tune;            /* launch shape of the loop (2-D masks): 0 default; -1 tune
+                          (times every candidate of PFISTA_TUNE_CANDIDATES on this
+                          solve's chain once, cached per device architecture and
+                          plan shape, persisted in $PFISTA_TUNE_CACHE if set);
+                          k >= 1 candidate k - 1 */
 } pfista_params;
 
 typedef struct {
@@ -209,6 +222,8 @@ typedef struct {
   double inv_l;           /* 1/L used */
   double bnorm;           /* ||b|| */
   long long normal_applies; /* A^H A applications in the loop */
+  int candidate;          /* launch shape used */
+  double tune_us;         /* tuner's time of one chain (0 if not timed) */
 } pfista_report;
 
 /* Algorithm 4 on the caller's stream.  Setup (FP64 ||b||, optional power
@@ -309,12 +324,6 @@ typedef struct {
 } pfista_slice_desc;
 
 typedef struct pfista_batch pfista_batch;
-
-/* Launch-shape candidates a group can be forced to (params.tune = k + 1):
- * candidate k uses radix schedule k % 2 (0: default, 1: twice the lanes per
- * transform), fuses the Horner row passes unless (k / 2) % 2, and multiplies
- * the rows per coil-combine block by 2^(k / 4). */
-#define PFISTA_TUNE_CANDIDATES 12
 
 /* Validate and group `count` slices (HOST array); count >= 0, at most 65535
  * coil images per group.  chunk_bytes > 0 caps the coil-map bytes of a group

@@ -45,13 +45,14 @@ class _Params(ctypes.Structure):
                 ("check_every", ctypes.c_int), ("tol", ctypes.c_double),
                 ("f_stop", ctypes.c_double), ("eval_objective", ctypes.c_int),
                 ("k0", ctypes.c_int), ("graph_iters", ctypes.c_int), ("momentum", ctypes.c_int),
-                ("bnorm", ctypes.c_double)]
+                ("bnorm", ctypes.c_double), ("tune", ctypes.c_int)]
 
 
 class _Report(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("status", ctypes.c_int), ("objective", ctypes.c_double),
                 ("rel_change", ctypes.c_double), ("l1", ctypes.c_double), ("inv_l", ctypes.c_double),
-                ("bnorm", ctypes.c_double), ("normal_applies", ctypes.c_longlong)]
+                ("bnorm", ctypes.c_double), ("normal_applies", ctypes.c_longlong),
+                ("candidate", ctypes.c_int), ("tune_us", ctypes.c_double)]
 
 
 class _SliceDesc(ctypes.Structure):
@@ -347,9 +348,10 @@ def profile_normal(plan, sens, mask, x, y, reps=50, stream=None) -> list:
 
 def solve(plan, sens, mask, b, x, lam, degree=3, coef=None, max_iter=50, inv_l=0.0, power_iters=30,
           check_every=None, tol=0.0, f_stop=0.0, eval_objective=False, z=None, k0=0, graph_iters=0,
-          history=False, stream=None, raise_on_diverge=True, momentum=True, bnorm=0.0):
+          history=False, stream=None, raise_on_diverge=True, momentum=True, bnorm=0.0, tune=0):
     """Algorithm 4 through ``pfista_solve``; returns the report as a dict (with
-    ``history`` when asked)."""
+    ``history`` when asked).  ``tune``: 0 default launch shape, -1 tuned and
+    cached, ``k >= 1`` candidate ``k - 1``."""
     c = _cplx()
     lib = load_library()
     ce = max_iter if check_every is None else check_every
@@ -361,7 +363,7 @@ def solve(plan, sens, mask, b, x, lam, degree=3, coef=None, max_iter=50, inv_l=0
     prm = _Params(float(lam), float(inv_l), int(power_iters), int(degree),
                   ctypes.cast(carr, ctypes.POINTER(ctypes.c_double)) if carr is not None else None,
                   int(max_iter), ce, float(tol), float(f_stop), int(bool(eval_objective or history)),
-                  int(k0), int(graph_iters), int(bool(momentum)), float(bnorm))
+                  int(k0), int(graph_iters), int(bool(momentum)), float(bnorm), int(tune))
     nh = max(1, -(-int(max_iter) // ce))
     hist = (ctypes.c_double * nh)() if history else None
     rep = _Report()

@@ -506,18 +506,32 @@ Chain make_chain(double inv_l, const std::vector<double> &c, const float2 *pre_x
   return ch;
 }
 
+// launch-shape candidate `cand` (see PFISTA_TUNE_CANDIDATES): radix schedule
+// cand % 2, separate Horner row passes if (cand / 2) % 2, rows per coil-combine
+// block times 2^(cand / 4); only 2-D masks have alternatives
+int plan_candidate_ok(const pfista_desc &d, int cand) { return d.mask_kind == PFISTA_MASK_2D ? cand : 0; }
+
 void grad_poly_op(const pfista_desc &d, const pfista_c32 *sens, const uint8_t *mask, double inv_l,
                   const std::vector<double> &c, const float2 *pre_x, const float2 *pre_w, float2 *g,
-                  float2 *out, void *ws, hipStream_t st, int *k_inc) {
+                  float2 *out, void *ws, hipStream_t st, int *k_inc, int cand = 0) {
   const int deg = (int)c.size() - 1;
   const Layout L = layout(d);
   float2 *t = at<float2>(ws, L.t);
   const Chain ch = make_chain(inv_l, c, pre_x, pre_w, g, out);
+  cand = plan_candidate_ok(d, cand);
+  Shape sh = shape_of(d);
+  sh.rpw_mult = 1 << (cand / 4);
+  sh.fused = (cand / 2) % 2 ? 0 : 1;
   if (ch.m > 0)
-    PF_DISPATCH(d.n, Ops<NN>::chain(shape_of(d), F2(sens), mask, ch.x0, ch.m, ch.alpha, ch.beta, ch.w, ch.y, t, st,
-                                    k_inc));
+    PF_DISPATCH_V(d.n, cand % 2, Ops<NN, VV>::chain(sh, F2(sens), mask, ch.x0, ch.m, ch.alpha, ch.beta, ch.w, ch.y,
+                                                    t, st, k_inc));
   if (deg == 0 && !pre_x) pf::k_scale<<<blocks_for(L.n_img), 256, 0, st>>>(g, out, L.n_img, (float)c[0]);
 }
+
+// the plan tuner (defined with the batch tuner further down)
+int tune_plan(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *mask, const std::vector<double> &c,
+              double inv_l, const float2 *x0, float2 *g, float2 *pg, void *ws, hipStream_t st, int &best,
+              double &best_us);
 
 void poly_op(const pfista_desc &d, const pfista_c32 *sens, const uint8_t *mask, double inv_l,
              const std::vector<double> &c, const float2 *g, float2 *out, void *ws, hipStream_t st) {
@@ -884,6 +898,8 @@ int pfista_solve(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *ma
   if (prm->k0 < 0 || (prm->k0 > 0 && !z_io)) return fail(PFISTA_EINVAL, "resume (k0 > 0) needs z_io");
   if (prm->inv_l < 0.0) return fail(PFISTA_EINVAL, "inv_l < 0");
   if (prm->inv_l == 0.0 && prm->power_iters < 1) return fail(PFISTA_EINVAL, "inv_l == 0 needs power_iters >= 1");
+  if (prm->tune < -1 || prm->tune > PFISTA_TUNE_CANDIDATES)
+    return fail(PFISTA_EINVAL, "tune outside -1..%d", PFISTA_TUNE_CANDIDATES);
   std::vector<double> c;
   if (prm->coef) {
     if (prm->degree < 0 || prm->degree > kMaxDegree) return fail(PFISTA_UNSUPPORTED, "degree %d", prm->degree);
@@ -958,10 +974,20 @@ int pfista_solve(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *ma
   const int deg = (int)c.size() - 1;
   const float lam = (float)prm->lambda;
   const int nstep = (d.n / 16) * (d.n / 16) * d.slices;
+  // launch shape: forced, default, or tuned (cached) on the chain of this solve
+  int cand = 0;
+  double cand_us = 0.0;
+  if (prm->tune >= 1) {
+    cand = plan_candidate_ok(d, prm->tune - 1);
+  } else if (prm->tune == -1 && d.mask_kind == PFISTA_MASK_2D) {
+    PF_TRY(tune_plan(p, sens, mask, c, inv_l, ahb, g, pgb, ws, stream, cand, cand_us));
+  }
+  r.candidate = cand;
+  r.tune_us = cand_us;
   auto body = [&]() {
     // g = N' z - A'^H b' then pg = p(N') g as one chain of d + 1 applies (its
     // first kernel advances the iteration counter k); then the fused step
-    grad_poly_op(d, sens, mask, inv_l, c, zb, ahb, g, pgb, ws, stream, &ds->k);
+    grad_poly_op(d, sens, mask, inv_l, c, zb, ahb, g, pgb, ws, stream, &ds->k, cand);
     const float2 *pg = deg == 0 ? g : pgb;
     const float pg_scale = deg == 0 ? (float)c[0] : 1.f;
     // momentum off (Algorithms 1 and 3): beta = 0, so z_(k+1) = x_(k+1)
@@ -1098,8 +1124,28 @@ void group_chain(const BGroup &G, const Shape &sh, int V, void *ws, const Chain 
   PF_DISPATCH_V(G.n, V, Ops<NN, VV>::chain(sh, sens, mask, ch.x0, ch.m, ch.alpha, ch.beta, ch.w, ch.y, t, st, k_inc));
 }
 
-// ---- tuner cache: per device architecture and group signature; optionally
-// persisted as "key candidate microseconds" lines in $PFISTA_TUNE_CACHE
+// architecture name of a device without its feature suffix ("gfx950")
+std::mutex g_arch_mu;
+std::vector<std::string> g_arch;
+
+std::string device_arch(int dev) {
+  std::lock_guard<std::mutex> lk(g_arch_mu);
+  if ((int)g_arch.size() <= dev) g_arch.resize(dev + 1);
+  if (g_arch[dev].empty()) {
+    hipDeviceProp_t prop;
+    std::string a = "unknown";
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+      a = prop.gcnArchName;
+      const size_t colon = a.find(':');
+      if (colon != std::string::npos) a.resize(colon);
+    }
+    g_arch[dev] = a;
+  }
+  return g_arch[dev];
+}
+
+// ---- tuner cache: per device architecture and plan or group signature;
+// optionally persisted as "key candidate microseconds" lines in $PFISTA_TUNE_CACHE
 std::mutex g_tune_mu;
 std::vector<std::pair<std::string, std::pair<int, double>>> g_tune;
 bool g_tune_read = false;
@@ -1194,6 +1240,60 @@ int tune_group(const BGroup &G, void *ws, const std::vector<double> &c, hipStrea
   return rc;
 }
 
+// Plan solves: time one gradient + polynomial chain from x0 for every distinct
+// candidate (one warm-up, three timed), cached per architecture and plan shape.
+int tune_plan(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *mask, const std::vector<double> &c,
+              double inv_l, const float2 *x0, float2 *g, float2 *pg, void *ws, hipStream_t st, int &best,
+              double &best_us) {
+  const pfista_desc &d = p->d;
+  const int deg = (int)c.size() - 1;
+  char key[320];
+  snprintf(key, sizeof key, "%s|plan|n%d|s%d|c%d|L%d|d%d", device_arch(p->device).c_str(), d.n, d.slices, d.coils,
+           d.haar_levels, deg);
+  if (tune_lookup(key, best, best_us)) return PFISTA_OK;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  PF_HIP(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(PFISTA_EHIP, "tuner: event create failed");
+  }
+  best = 0;
+  best_us = 0.0;
+  int rc = PFISTA_OK;
+  std::vector<int> seen;
+  for (int k = 0; k < PFISTA_TUNE_CANDIDATES && rc == PFISTA_OK; ++k) {
+    Shape sh = shape_of(d);
+    sh.rpw_mult = 1 << (k / 4);
+    sh.fused = (k / 2) % 2 ? 0 : 1;
+    int rpw = 0;
+    PF_DISPATCH_V(d.n, k % 2, rpw = Ops<NN, VV>::rows_per_block(sh));
+    const int sig = ((k % 2) * 2 + sh.fused) * 1024 + rpw;
+    if (std::find(seen.begin(), seen.end(), sig) != seen.end()) continue;
+    seen.push_back(sig);
+    grad_poly_op(d, sens, mask, inv_l, c, x0, x0, g, pg, ws, st, nullptr, k);
+    hipError_t he = hipEventRecord(e0, st);
+    for (int r = 0; r < 3 && he == hipSuccess; ++r) grad_poly_op(d, sens, mask, inv_l, c, x0, x0, g, pg, ws, st, nullptr, k);
+    if (he == hipSuccess) he = hipEventRecord(e1, st);
+    if (he == hipSuccess) he = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    if (he != hipSuccess) {
+      rc = fail(PFISTA_EHIP, "tuner: %s", hipGetErrorString(he));
+      break;
+    }
+    rc = launch_status("tuner");
+    const double us = 1e3 * ms / 3.0;
+    if (seen.size() == 1 || us < best_us) {
+      best = k;
+      best_us = us;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc == PFISTA_OK) tune_store(key, best, best_us);
+  return rc;
+}
+
 int check_batch_params(const pfista_batch_params *prm, std::vector<double> &c) {
   if (!prm) return fail(PFISTA_EINVAL, "params is NULL");
   if (prm->max_iter < 0) return fail(PFISTA_EINVAL, "max_iter < 0");
@@ -1250,14 +1350,7 @@ int pfista_batch_create(pfista_batch **out, const pfista_slice_desc *slices, int
     delete b;
     return fail(PFISTA_EHIP, "hipGetDevice failed");
   }
-  hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, b->device) == hipSuccess) {
-    b->arch = prop.gcnArchName;
-    const size_t colon = b->arch.find(':');
-    if (colon != std::string::npos) b->arch.resize(colon);
-  } else {
-    b->arch = "unknown";
-  }
+  b->arch = device_arch(b->device);
   // groups in ascending (n, levels), slices in caller order inside a group
   std::vector<int> order(count);
   for (int s = 0; s < count; ++s) order[s] = s;

@@ -102,3 +102,61 @@ def test_null_batch_is_rejected(lib):
                                 None, None, None)
     assert rc == -1 and b"batch" in lib.pfista_last_error()
     assert lib.pfista_batch_workspace_bytes(None) == 0 and lib.pfista_batch_groups(None) == 0
+
+
+_STRUCTS = {"pfista_desc": "_Desc", "pfista_params": "_Params", "pfista_report": "_Report",
+            "pfista_slice_desc": "_SliceDesc", "pfista_batch_params": "_BatchParams",
+            "pfista_slice_report": "_SliceReport", "pfista_group_report": "_GroupReport",
+            "pfista_batch_report": "_BatchReport", "pfista_unroll_params": "_UnrollParams"}
+
+
+def _c_field_names(header: str, struct: str):
+    """Member names of ``typedef struct { ... } struct;`` in the header text."""
+    import re
+    end = header.index("} " + struct + ";")
+    start = header.rindex("typedef struct {", 0, end)
+    body = re.sub(r"/\*.*?\*/", "", header[start + len("typedef struct {"):end], flags=re.S)
+    names = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if decl:
+            names.append(re.findall(r"[A-Za-z_]\w*", decl)[-1])
+    return names
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """Every ctypes mirror has the C struct's size, member names (in order) and
+    offsets, as a host C compiler lays out the header's structs."""
+    import shutil
+    import subprocess
+    import paper_2204_10252_amd as pf
+
+    if shutil.which("gcc") is None:
+        pytest.skip("no host C compiler")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    header = open(os.path.join(root, "include", "pfista.h")).read()
+    fields = {s: _c_field_names(header, s) for s in _STRUCTS}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "pfista.h"', "int main(void) {"]
+    for s, names in fields.items():
+        lines.append(f'  printf("{s} size %zu\\n", sizeof({s}));')
+        for f in names:
+            lines.append(f'  printf("{s} {f} %zu\\n", offsetof({s}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(root, "include"),
+                    "-I", "/opt/rocm/include", str(src), "-o", str(exe)], check=True, capture_output=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    c = {}
+    for line in out:
+        if line:
+            s, f, v = line.split()
+            c[(s, f)] = int(v)
+    for s, py in _STRUCTS.items():
+        cls = getattr(pf, py)
+        py_names = [n.rstrip("_") for n, _ in cls._fields_]
+        assert py_names == fields[s], s
+        assert ctypes.sizeof(cls) == c[(s, "size")], s
+        for (n, _), f in zip(cls._fields_, fields[s]):
+            assert getattr(cls, n).offset == c[(s, f)], (s, f)

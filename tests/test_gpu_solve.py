@@ -162,3 +162,70 @@ def test_pgd_ppgd_and_polynomial_designs(c1, design):
              max_iter=30, inv_l=inv_l, momentum=False)
     yo, _ = orc.pgd(s128, inp["mask"], bn, inv_l, inp["lam"], coef, inp["levels"], 30)
     assert rel(x.cpu().numpy(), yo) <= 1e-4
+
+
+@pytest.mark.parametrize("tune", list(range(1, 13)))
+def test_every_forced_launch_shape_matches_oracle(c1, tune):
+    # every launch-shape candidate computes the same iteration
+    import torch
+    import paper_2204_10252_amd as pf
+    inp, sens, s128, b, bn, inv_l = c1
+    plan = gpu_plan(inp)
+    coef = [float(c) for c in orc.l2_poly_coefficients(3)]
+    x = torch.empty((1, inp["n"], inp["n"]), dtype=torch.complex64, device="cuda")
+    rep = pf.solve(plan, to_dev(sens), to_dev(inp["mask"]), to_dev(b), x, inp["lam"], coef=coef,
+                   max_iter=30, inv_l=inv_l, tune=tune)
+    assert rep["candidate"] == tune - 1 and rep["tune_us"] == 0.0
+    xo, _, _ = orc.pfista(s128, inp["mask"], bn, inv_l, inp["lam"], coef, inp["levels"], 30)
+    assert rel(x.cpu().numpy(), xo) <= 1e-4
+
+
+def test_tuned_solve_workload2_is_cached_and_matches_oracle():
+    import torch
+    import paper_2204_10252_amd as pf
+    inp, sens, s128, b, bn, inv_l = problem(2)
+    plan = gpu_plan(inp)
+    coef = [float(c) for c in orc.l2_poly_coefficients(3)]
+    args = (plan, to_dev(sens), to_dev(inp["mask"]), to_dev(b))
+    x = torch.empty((1, 256, 256), dtype=torch.complex64, device="cuda")
+    r1 = pf.solve(*args, x, inp["lam"], coef=coef, max_iter=15, inv_l=inv_l, tune=-1)
+    assert 0 <= r1["candidate"] < pf.TUNE_CANDIDATES and r1["tune_us"] > 0.0
+    xo, _, _ = orc.pfista(s128, inp["mask"], bn, inv_l, inp["lam"], coef, inp["levels"], 15)
+    assert rel(x.cpu().numpy(), xo) <= 1e-4
+    x2 = torch.empty_like(x)
+    r2 = pf.solve(*args, x2, inp["lam"], coef=coef, max_iter=15, inv_l=inv_l, tune=-1)
+    assert (r2["candidate"], r2["tune_us"]) == (r1["candidate"], r1["tune_us"])
+    assert torch.equal(x, x2)
+
+
+def test_phase_encode_plan_ignores_forced_shape():
+    # phase-encode masks have one launch shape: a forced candidate runs it
+    import torch
+    import paper_2204_10252_amd as pf
+    inp = make_inputs(3, 1)
+    sens = c64(inp["sens"])
+    s128 = sens.astype(np.complex128)
+    b = c64(orc.kspace_data(s128, inp["mask"], inp["phantom"], inp["noise"]))
+    bn = b.astype(np.complex128) / np.linalg.norm(b.astype(np.complex128))
+    inv_l = 1.0 / 1.01      # ||A||^2 <= 1 for root-sum-of-squares normalised maps
+    plan = gpu_plan(inp)
+    coef = [float(c) for c in orc.l2_poly_coefficients(2)]
+    x = torch.empty((1, inp["n"], inp["n"]), dtype=torch.complex64, device="cuda")
+    rep = pf.solve(plan, to_dev(sens), to_dev(inp["mask"]), to_dev(b), x, inp["lam"], coef=coef,
+                   max_iter=5, inv_l=inv_l, tune=6)
+    assert rep["candidate"] == 0
+    xo, _, _ = orc.pfista(s128, inp["mask"], bn, inv_l, inp["lam"], coef, inp["levels"], 5)
+    assert rel(x.cpu().numpy(), xo) <= 1e-4
+
+
+@pytest.mark.parametrize("tune", [-2, 13])
+def test_tune_outside_range_is_rejected(c1, tune):
+    import torch
+    import paper_2204_10252_amd as pf
+    inp, sens, s128, b, bn, inv_l = c1
+    plan = gpu_plan(inp)
+    x = torch.zeros((1, inp["n"], inp["n"]), dtype=torch.complex64, device="cuda")
+    with pytest.raises(pf.PfistaError) as e:
+        pf.solve(plan, to_dev(sens), to_dev(inp["mask"]), to_dev(b), x, inp["lam"], degree=1,
+                 max_iter=2, inv_l=inv_l, tune=tune)
+    assert e.value.code == pf.EINVAL
