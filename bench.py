@@ -649,6 +649,14 @@ def main():
                          "passes_us": {m[0]: round(t * 1e3, 3) for m, t in zip(model, pass_ms)}})
         apply_us = sum(pass_ms[:3]) * 1e3
         roofline["normal_apply_us"] = round(apply_us, 3)
+        # whole-apply figure: the operator's own bytes (coil maps once, x in, y out, mask)
+        # over the loop's time per apply (step and hand-overs included)
+        alg_apply = 8 * plan.n * plan.n * (plan.coils + 2) + plan.n * plan.n
+        loop_apply_s = dt / applies
+        roofline["apply_level"] = {"algorithmic_bytes_per_apply": alg_apply,
+                                   "us_per_apply_in_loop": round(loop_apply_s * 1e6, 3),
+                                   "hbm_gbs": round(alg_apply / loop_apply_s / 1e9, 1),
+                                   "hbm_frac": round(alg_apply / loop_apply_s / 1e9 / PEAK_HBM_GBS, 4)}
         log(f"passes (us): {roofline['passes_us']}")
         cold = cold_warm_apply(torch, pf, plan, sens, mask, x, y, stream)
         log(f"apply cold/warm (us): {cold}")

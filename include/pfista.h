@@ -70,7 +70,9 @@ typedef enum {
 typedef enum { PFISTA_MASK_2D = 0, PFISTA_MASK_1D = 1, PFISTA_TOEPLITZ = 2 } pfista_mask_kind;
 
 /* Problem shape.  n in {64, 128, 160, 192, 256, 320, 384, 512} (radices 2, 3,
- * 5); 1 <= haar_levels <= 4; coils >= 1; slices >= 0; slices * coils <= 65535. */
+ * 5); 1 <= haar_levels <= 4; coils >= 1; slices >= 0; slices * coils <= 65535;
+ * phase-encode plans also need coils * n * n * 8 < 2^31 (the coil maps of one
+ * slice, e.g. at most 1023 coils at n = 512). */
 typedef struct {
   int n;
   int coils;

@@ -201,6 +201,101 @@ template <int R, int DIR> __device__ __forceinline__ void dft(float2 *v) {
   }
 }
 
+// ------------------------------------------- butterflies on twiddled inputs
+// A stage with Ns > 1 multiplies inputs 1..R-1 of each butterfly by twiddles and
+// then takes a length-R DFT whose first operations are sums and differences of
+// input pairs.  For a pair (a, w b) both results come from one product folded
+// into FMAs: s = a + w b (four FMAs) and a - w b = 2 a - s (two FMAs), six
+// operations where the separate product, sum and difference take eight.
+#ifndef PF_FFT_FMA_TW
+#define PF_FFT_FMA_TW 1
+#endif
+__device__ __forceinline__ void bfly_tw(float2 &a, float2 &b, float2 w) {
+  float2 s;
+  s.x = __builtin_fmaf(w.x, b.x, a.x);
+  s.x = __builtin_fmaf(-w.y, b.y, s.x);
+  s.y = __builtin_fmaf(w.x, b.y, a.y);
+  s.y = __builtin_fmaf(w.y, b.x, s.y);
+  b = make_float2(__builtin_fmaf(2.f, a.x, -s.x), __builtin_fmaf(2.f, a.y, -s.y));
+  a = s;
+}
+
+// length-R2 DFT (R2 = 2 or 4) of c[n] w[n], with w[0] = 1 unless TW0
+template <int R2, int DIR, bool TW0>
+__device__ __forceinline__ void dft_in_tw(float2 *c, const float2 *w) {
+  static_assert(R2 == 2 || R2 == 4, "twiddled inner DFTs of length 2 or 4");
+  if constexpr (R2 == 2) {
+    if constexpr (TW0) c[0] = cmul(c[0], w[0]);
+    bfly_tw(c[0], c[1], w[1]);
+  } else {
+    float2 a0 = c[0], a2 = c[2], u1 = cmul(c[1], w[1]), a3 = c[3];
+    if constexpr (TW0) a0 = cmul(a0, w[0]);
+    bfly_tw(a0, a2, w[2]);            // a0 = t0 = x0 + x2, a2 = t1 = x0 - x2
+    bfly_tw(u1, a3, w[3]);            // u1 = t2 = x1 + x3, a3 = x1 - x3
+    const float2 t3 = mul_i<DIR>(a3);
+    c[0] = cadd(a0, u1);
+    c[2] = csub(a0, u1);
+    c[1] = cadd(a2, t3);
+    c[3] = csub(a2, t3);
+  }
+}
+
+// length-R DFT of v[r] w_r with w_0 = 1 and w_r = w[r - 1] (the twiddles of a stage)
+template <int R1, int R2, int DIR>
+__device__ __forceinline__ void dft_split_tw(float2 *v, const float2 *w) {
+  constexpr int R = R1 * R2;
+  float2 y[R];
+#pragma unroll
+  for (int n1 = 0; n1 < R1; ++n1) {
+    float2 col[R2], wc[R2];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) {
+      col[n2] = v[n1 + R1 * n2];
+      wc[n2] = (n1 + R1 * n2) ? w[n1 + R1 * n2 - 1] : make_float2(1.f, 0.f);
+    }
+    if (n1 == 0)
+      dft_in_tw<R2, DIR, false>(col, wc);
+    else
+      dft_in_tw<R2, DIR, true>(col, wc);
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) y[n1 * R2 + k2] = twiddle_small<R, DIR>(col[k2], n1 * k2);
+  }
+#pragma unroll
+  for (int k2 = 0; k2 < R2; ++k2) {
+    float2 row[R1];
+#pragma unroll
+    for (int n1 = 0; n1 < R1; ++n1) row[n1] = y[n1 * R2 + k2];
+    dft<R1, DIR>(row);
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) v[k2 + R2 * k1] = row[k1];
+  }
+}
+
+template <int R, int DIR> __device__ __forceinline__ void dft_tw(float2 *v, const float2 *w) {
+  if constexpr (R == 2) {
+    bfly_tw(v[0], v[1], w[0]);
+  } else if constexpr (R == 4) {
+    const float2 w4[4] = {make_float2(1.f, 0.f), w[0], w[1], w[2]};
+    dft_in_tw<4, DIR, false>(v, w4);
+  } else if constexpr (R == 6) {
+    dft_split_tw<3, 2, DIR>(v, w);
+  } else if constexpr (R == 8) {
+    dft_split_tw<4, 2, DIR>(v, w);
+  } else if constexpr (R == 10) {
+    dft_split_tw<5, 2, DIR>(v, w);
+  } else if constexpr (R == 12) {
+    dft_split_tw<3, 4, DIR>(v, w);
+  } else if constexpr (R == 16) {
+    dft_split_tw<4, 4, DIR>(v, w);
+  } else if constexpr (R == 20) {
+    dft_split_tw<5, 4, DIR>(v, w);
+  } else {
+#pragma unroll
+    for (int r = 1; r < R; ++r) v[r] = cmul(v[r], w[r - 1]);
+    dft<R, DIR>(v);
+  }
+}
+
 // ------------------------------------------------------------------ plans
 // Radix list (forward order); the inverse runs the mirrored list.
 template <int N_, int T_, int... Rs> struct Plan {
@@ -265,14 +360,22 @@ __device__ __forceinline__ void stage_compute(float2 *v, int j0, const float2 *t
     if constexpr (NS > 1) {
       const int j = j0 + b * PL::T;
       const float2 *tk = tw + TwLayout<PL>::off(S) + (j % NS) * (R - 1);
+      float2 w[R - 1];
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        float2 w = tk[r - 1];
-        if (DIR > 0) w.y = -w.y;
-        v[b * R + r] = cmul(v[b * R + r], w);
+        w[r - 1] = tk[r - 1];
+        if (DIR > 0) w[r - 1].y = -w[r - 1].y;
       }
+#if PF_FFT_FMA_TW
+      dft_tw<R, DIR>(v + b * R, w);
+#else
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[b * R + r] = cmul(v[b * R + r], w[r - 1]);
+      dft<R, DIR>(v + b * R);
+#endif
+    } else {
+      dft<R, DIR>(v + b * R);
     }
-    dft<R, DIR>(v + b * R);
   }
 }
 

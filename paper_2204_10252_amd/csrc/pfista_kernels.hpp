@@ -93,13 +93,22 @@ template <class F, class I, int WAVES = 4> struct PairGeo {
 };
 template <int N> struct TwBlock;
 template <int N> struct TwBase;
-template <int N, int V = 0> struct Geo : PairGeo<typename PlansV<N, V>::F, typename PlansV<N, V>::I> {
+template <int N, int V = 0, int W = 4>
+struct Geo : PairGeo<typename PlansV<N, V>::F, typename PlansV<N, V>::I, W> {
   using F = typename PlansV<N, V>::F;
   using I = typename PlansV<N, V>::I;
   // offsets of this geometry's forward / inverse twiddle tables in g_tw
   static constexpr int TWF = TwBase<N>::v + (V == 0 ? TwBlock<N>::f : TwBlock<N>::fa);
   static constexpr int TWI = TwBase<N>::v + (V == 0 ? TwBlock<N>::i : TwBlock<N>::ia);
 };
+// Waves per column-pass workgroup: 4, except that a doubled-lane schedule
+// (variant 1) with 32 lanes per transform holds two columns per wave and takes 8
+// waves, so that its workgroups still span 16 columns (128 bytes of every row).
+template <int N, int V> struct ColWaves {
+  static constexpr int t = PlansV<N, V>::F::T;
+  static constexpr int v = (V == 1 && t / 4 > 4) ? t / 4 : 4;
+};
+template <int N, int V> using ColGeo = Geo<N, V, ColWaves<N, V>::v>;
 // the phase-encode kernel's blocks span 16 columns (128 B of every row of a
 // coil map) so that no cache line of the streamed coil maps is split between
 // blocks
@@ -246,18 +255,19 @@ template <int MASK1D> __device__ __forceinline__ bool sampled(const uint8_t *mas
 }
 
 template <int N, int MODE, int MASK1D, int V = 0>
-__global__ __launch_bounds__(256, 2) void k_col(float2 *__restrict__ t, const float2 *__restrict__ kin,
-                                             float2 *__restrict__ kout, const uint8_t *__restrict__ mask,
-                                             int C, float a_scale, float b_scale,
-                                             double *__restrict__ partials, const int *__restrict__ cs) {
-  using Gm = Geo<N, V>;
+__global__ __launch_bounds__((64 * ColWaves<N, V>::v), (8 / ColWaves<N, V>::v)) void k_col(
+    float2 *__restrict__ t, const float2 *__restrict__ kin, float2 *__restrict__ kout,
+    const uint8_t *__restrict__ mask, int C, float a_scale, float b_scale, double *__restrict__ partials,
+    const int *__restrict__ cs) {
+  using Gm = ColGeo<N, V>;
+  static_assert(N % Gm::COLS == 0, "column workgroups must tile the image side");
   using F = typename Gm::F;
   using I = typename Gm::I;
   constexpr int T = Gm::T;
   __shared__ float2 s_twF[TwLayout<F>::size()];
   __shared__ float2 s_twI[TwLayout<I>::size()];
   __shared__ float2 s_buf[Gm::COLS * Gm::LDSN];
-  __shared__ double s_red[4];
+  __shared__ double s_red[Gm::THREADS / 64];
   const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
   const int ci = ln % Gm::CPW, col = wv * Gm::CPW + ci, j0 = ln / Gm::CPW;
   // this column's exchange buffer: the wave's columns interleaved element by element
@@ -350,8 +360,12 @@ __global__ __launch_bounds__(256, 2) void k_col(float2 *__restrict__ t, const fl
     acc = wave_sum_d(acc);
     if (ln == 0) s_red[wv] = acc;
     __syncthreads();
-    if (threadIdx.x == 0)
-      partials[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = ((s_red[0] + s_red[1]) + s_red[2]) + s_red[3];
+    if (threadIdx.x == 0) {
+      double sum = s_red[0];
+#pragma unroll
+      for (int q = 1; q < Gm::THREADS / 64; ++q) sum += s_red[q];
+      partials[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = sum;
+    }
   }
 }
 

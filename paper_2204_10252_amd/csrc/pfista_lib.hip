@@ -268,14 +268,15 @@ template <int N, int V = 0> struct Ops {
   template <int MODE>
   static void col(const Shape &d, float2 *t, const float2 *kin, float2 *kout, const uint8_t *mask,
                   float a, float b, double *partials, hipStream_t st) {
-    const dim3 grid(N / Gm::COLS, d.images);
+    using Gc = pf::ColGeo<N, V>;
+    const dim3 grid(N / Gc::COLS, d.images);
     if constexpr (V == 0) {
       if (d.mask_kind == PFISTA_MASK_1D) {
-        pf::k_col<N, MODE, 1, V><<<grid, Gm::THREADS, 0, st>>>(t, kin, kout, mask, d.coils, a, b, partials, d.cs);
+        pf::k_col<N, MODE, 1, V><<<grid, Gc::THREADS, 0, st>>>(t, kin, kout, mask, d.coils, a, b, partials, d.cs);
         return;
       }
     }
-    pf::k_col<N, MODE, 0, V><<<grid, Gm::THREADS, 0, st>>>(t, kin, kout, mask, d.coils, a, b, partials, d.cs);
+    pf::k_col<N, MODE, 0, V><<<grid, Gc::THREADS, 0, st>>>(t, kin, kout, mask, d.coils, a, b, partials, d.cs);
   }
 
   // rows per block of the coil-combine passes: by default the largest power of
@@ -352,7 +353,7 @@ template <int N, int V = 0> struct Ops {
 
   // FP64 partial sums the residual column pass writes: N / COLS per coil image,
   // image-major
-  static int resid_per_image() { return N / Gm::COLS; }
+  static int resid_per_image() { return N / pf::ColGeo<N, V>::COLS; }
   static int resid_blocks(const Shape &d) { return resid_per_image() * d.images; }
 
   // kernel passes timed by pfista_profile_normal: the three passes of one apply
@@ -628,6 +629,10 @@ int pfista_plan_create(pfista_plan **out, const pfista_desc *d) {
     return fail(PFISTA_UNSUPPORTED, "haar_levels %d outside 1..4", d->haar_levels);
   if (d->mask_kind != PFISTA_MASK_2D && d->mask_kind != PFISTA_MASK_1D && d->mask_kind != PFISTA_TOEPLITZ)
     return fail(PFISTA_EINVAL, "mask_kind %d", d->mask_kind);
+  // the phase-encode kernel addresses one slice's coil maps with 32-bit byte offsets
+  if (d->mask_kind == PFISTA_MASK_1D && (long long)d->coils * d->n * d->n * 8 > 2147483647ll)
+    return fail(PFISTA_UNSUPPORTED, "phase-encode plans need coils * n * n * 8 < 2^31 bytes per slice (got %d coils)",
+                d->coils);
   if (d->mask_kind == PFISTA_TOEPLITZ && !supported_toeplitz_n(d->n))
     return fail(PFISTA_UNSUPPORTED, "Toeplitz plans need n in {64,128,160,192,256} (got %d)", d->n);
   PF_TRY(ensure_twiddles());

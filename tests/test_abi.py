@@ -47,6 +47,7 @@ def _desc(n=64, coils=2, slices=1, levels=3, kind=0):
     (dict(n=100), -2), (dict(n=96), -2), (dict(levels=0), -2), (dict(levels=5), -2),
     (dict(coils=0), -1), (dict(slices=-1), -1), (dict(kind=7), -1),
     (dict(coils=1000, slices=100), -2), (dict(n=320, kind=2), -2), (dict(n=512, kind=2), -2),
+    (dict(n=512, coils=1024, slices=1, kind=1), -2), (dict(n=384, coils=1821, slices=1, kind=1), -2),
 ])
 def test_plan_validation_before_any_gpu_call(lib, desc, code):
     h = ctypes.c_void_p()
