@@ -404,35 +404,43 @@ def grad_benchmark(torch, pf, dev, stream, reps=5):
     b += torch.from_numpy(inp["noise"].astype(np.complex64)).to(dev) * mask[:, None].to(torch.complex64)
     inv_l = 1.0 / (1.01 * pf.power_iteration(plan, sens, mask, 30))
     K, d = w.iters, w.degree
-    u = pf.Unrolled(plan, d, K, inv_l, ckpt_every=5)
     coef = pf.poly_coefficients(d)
     scale = float(np.sqrt(inv_l) * torch.linalg.vector_norm(b).item())
     x = torch.empty((S, n, n), dtype=torch.complex64, device=dev)
-    tf, tb = [], []
-    with torch.cuda.stream(stream):
-        for r in range(reps + 1):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            u.forward(sens, mask, b, x, w.lam, coef, stream=stream)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            xbar = (2.0 * scale / x.numel()) * (scale * x - img)
-            torch.cuda.synchronize()
-            t2 = time.perf_counter()
-            grad = u.backward(sens, mask, xbar, w.lam, coef, stream=stream)
-            torch.cuda.synchronize()
-            t3 = time.perf_counter()
-            if r > 0:
-                tf.append(t1 - t0)
-                tb.append(t3 - t2)
-    fwd, bwd = sorted(tf)[len(tf) // 2], sorted(tb)[len(tb) // 2]
     applies_f, applies_b = K * (d + 1), 2 * K * (d + 1)
-    return {"workload": "8 slices 192x192, 12 coils, R=5, d=4, 20 unrolled iterations, checkpoints every 5",
-            "forward_ms": round(1e3 * fwd, 3), "backward_ms": round(1e3 * bwd, 3),
-            "backward_over_forward": round(bwd / fwd, 3),
-            "applies_forward": applies_f, "applies_backward": applies_b,
-            "applies_per_s": round((applies_f + applies_b) / (fwd + bwd), 1),
-            "grad_lambda": grad[0], "grad_coef": grad[1]}
+    out = {"workload": "8 slices 192x192, 12 coils, R=5, d=4, 20 unrolled iterations, checkpoints every 5",
+           "applies_forward": applies_f, "applies_backward": applies_b}
+    # default launch shape, then the tuned one (the untimed first repetition tunes)
+    for label, tune in (("default", 0), ("tuned", -1)):
+        u = pf.Unrolled(plan, d, K, inv_l, ckpt_every=5, tune=tune)
+        tf, tb = [], []
+        with torch.cuda.stream(stream):
+            for r in range(reps + 1):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                u.forward(sens, mask, b, x, w.lam, coef, stream=stream)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                xbar = (2.0 * scale / x.numel()) * (scale * x - img)
+                torch.cuda.synchronize()
+                t2 = time.perf_counter()
+                grad = u.backward(sens, mask, xbar, w.lam, coef, stream=stream)
+                torch.cuda.synchronize()
+                t3 = time.perf_counter()
+                if r > 0:
+                    tf.append(t1 - t0)
+                    tb.append(t3 - t2)
+        fwd, bwd = sorted(tf)[len(tf) // 2], sorted(tb)[len(tb) // 2]
+        res = {"forward_ms": round(1e3 * fwd, 3), "backward_ms": round(1e3 * bwd, 3),
+               "backward_over_forward": round(bwd / fwd, 3),
+               "applies_per_s": round((applies_f + applies_b) / (fwd + bwd), 1),
+               "grad_lambda": grad[0], "grad_coef": grad[1]}
+        if label == "default":
+            out.update(res)
+        else:
+            out["tuned_launch_shape"] = res
+        del u
+    return out
 
 
 def toeplitz_benchmark(torch, pf, dev, stream, iters=50, graph_iters=10):

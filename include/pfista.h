@@ -289,6 +289,9 @@ typedef struct {
   int iters;           /* K >= 1 */
   int ckpt_every;      /* >= 1 (values above K act as K) */
   int momentum;        /* 1: FISTA momentum; 0: PGD / PPGD */
+  int tune;            /* launch shape, as pfista_params.tune (0 default, -1 tuned
+                          and cached, k >= 1 candidate k - 1); pass the same
+                          value to the forward and the backward pass */
 } pfista_unroll_params;
 
 /* Device bytes of the checkpoint buffer filled by the forward pass and read

@@ -84,7 +84,7 @@ class _BatchReport(ctypes.Structure):
 class _UnrollParams(ctypes.Structure):
     _fields_ = [("lambda_", ctypes.c_double), ("inv_l", ctypes.c_double), ("degree", ctypes.c_int),
                 ("coef", ctypes.POINTER(ctypes.c_double)), ("iters", ctypes.c_int), ("ckpt_every", ctypes.c_int),
-                ("momentum", ctypes.c_int)]
+                ("momentum", ctypes.c_int), ("tune", ctypes.c_int)]
 
 
 TUNE_CANDIDATES = 12
@@ -479,12 +479,13 @@ class Unrolled:
     """K unrolled iterations of Algorithm 4 on one plan, differentiable in the
     threshold and the polynomial coefficients (``pfista_unroll_forward`` /
     ``pfista_unroll_backward``).  Holds the checkpoint buffer of the last
-    forward pass and the workspace."""
+    forward pass and the workspace.  ``tune``: launch shape as in ``solve``."""
 
-    def __init__(self, plan, degree, iters, inv_l, ckpt_every=5, momentum=True):
+    def __init__(self, plan, degree, iters, inv_l, ckpt_every=5, momentum=True, tune=0):
         import torch
         self.plan, self.degree, self.iters = plan, int(degree), int(iters)
         self.inv_l, self.ckpt_every, self.momentum = float(inv_l), int(ckpt_every), bool(momentum)
+        self.tune = int(tune)
         lib = load_library()
         prm = self._params(0.0, [0.0] * (self.degree + 1))
         nck = int(lib.pfista_unroll_ckpt_bytes(plan.handle, ctypes.byref(prm)))
@@ -498,7 +499,7 @@ class Unrolled:
         self._carr = (ctypes.c_double * len(coef))(*[float(v) for v in coef])
         return _UnrollParams(float(lam), self.inv_l, len(coef) - 1,
                              ctypes.cast(self._carr, ctypes.POINTER(ctypes.c_double)), self.iters,
-                             self.ckpt_every, int(self.momentum))
+                             self.ckpt_every, int(self.momentum), self.tune)
 
     def forward(self, sens, mask, b, x, lam, coef, stream=None):
         c, pl = _cplx(), self.plan

@@ -93,22 +93,13 @@ template <class F, class I, int WAVES = 4> struct PairGeo {
 };
 template <int N> struct TwBlock;
 template <int N> struct TwBase;
-template <int N, int V = 0, int W = 4>
-struct Geo : PairGeo<typename PlansV<N, V>::F, typename PlansV<N, V>::I, W> {
+template <int N, int V = 0> struct Geo : PairGeo<typename PlansV<N, V>::F, typename PlansV<N, V>::I> {
   using F = typename PlansV<N, V>::F;
   using I = typename PlansV<N, V>::I;
   // offsets of this geometry's forward / inverse twiddle tables in g_tw
   static constexpr int TWF = TwBase<N>::v + (V == 0 ? TwBlock<N>::f : TwBlock<N>::fa);
   static constexpr int TWI = TwBase<N>::v + (V == 0 ? TwBlock<N>::i : TwBlock<N>::ia);
 };
-// Waves per column-pass workgroup: 4, except that a doubled-lane schedule
-// (variant 1) with 32 lanes per transform holds two columns per wave and takes 8
-// waves, so that its workgroups still span 16 columns (128 bytes of every row).
-template <int N, int V> struct ColWaves {
-  static constexpr int t = PlansV<N, V>::F::T;
-  static constexpr int v = (V == 1 && t / 4 > 4) ? t / 4 : 4;
-};
-template <int N, int V> using ColGeo = Geo<N, V, ColWaves<N, V>::v>;
 // the phase-encode kernel's blocks span 16 columns (128 B of every row of a
 // coil map) so that no cache line of the streamed coil maps is split between
 // blocks
@@ -255,11 +246,11 @@ template <int MASK1D> __device__ __forceinline__ bool sampled(const uint8_t *mas
 }
 
 template <int N, int MODE, int MASK1D, int V = 0>
-__global__ __launch_bounds__((64 * ColWaves<N, V>::v), (8 / ColWaves<N, V>::v)) void k_col(
-    float2 *__restrict__ t, const float2 *__restrict__ kin, float2 *__restrict__ kout,
-    const uint8_t *__restrict__ mask, int C, float a_scale, float b_scale, double *__restrict__ partials,
-    const int *__restrict__ cs) {
-  using Gm = ColGeo<N, V>;
+__global__ __launch_bounds__(256, 2) void k_col(float2 *__restrict__ t, const float2 *__restrict__ kin,
+                                             float2 *__restrict__ kout, const uint8_t *__restrict__ mask,
+                                             int C, float a_scale, float b_scale,
+                                             double *__restrict__ partials, const int *__restrict__ cs) {
+  using Gm = Geo<N, V>;
   static_assert(N % Gm::COLS == 0, "column workgroups must tile the image side");
   using F = typename Gm::F;
   using I = typename Gm::I;

@@ -268,15 +268,14 @@ template <int N, int V = 0> struct Ops {
   template <int MODE>
   static void col(const Shape &d, float2 *t, const float2 *kin, float2 *kout, const uint8_t *mask,
                   float a, float b, double *partials, hipStream_t st) {
-    using Gc = pf::ColGeo<N, V>;
-    const dim3 grid(N / Gc::COLS, d.images);
+    const dim3 grid(N / Gm::COLS, d.images);
     if constexpr (V == 0) {
       if (d.mask_kind == PFISTA_MASK_1D) {
-        pf::k_col<N, MODE, 1, V><<<grid, Gc::THREADS, 0, st>>>(t, kin, kout, mask, d.coils, a, b, partials, d.cs);
+        pf::k_col<N, MODE, 1, V><<<grid, Gm::THREADS, 0, st>>>(t, kin, kout, mask, d.coils, a, b, partials, d.cs);
         return;
       }
     }
-    pf::k_col<N, MODE, 0, V><<<grid, Gc::THREADS, 0, st>>>(t, kin, kout, mask, d.coils, a, b, partials, d.cs);
+    pf::k_col<N, MODE, 0, V><<<grid, Gm::THREADS, 0, st>>>(t, kin, kout, mask, d.coils, a, b, partials, d.cs);
   }
 
   // rows per block of the coil-combine passes: by default the largest power of
@@ -353,7 +352,7 @@ template <int N, int V = 0> struct Ops {
 
   // FP64 partial sums the residual column pass writes: N / COLS per coil image,
   // image-major
-  static int resid_per_image() { return N / pf::ColGeo<N, V>::COLS; }
+  static int resid_per_image() { return N / Gm::COLS; }
   static int resid_blocks(const Shape &d) { return resid_per_image() * d.images; }
 
   // kernel passes timed by pfista_profile_normal: the three passes of one apply
@@ -512,6 +511,17 @@ Chain make_chain(double inv_l, const std::vector<double> &c, const float2 *pre_x
 // block times 2^(cand / 4); only 2-D masks have alternatives
 int plan_candidate_ok(const pfista_desc &d, int cand) { return d.mask_kind == PFISTA_MASK_2D ? cand : 0; }
 
+// a plan's chain of applies in the launch shape of candidate `cand`
+void chain_shaped(const pfista_desc &d, int cand, const pfista_c32 *sens, const uint8_t *mask, const float2 *x0,
+                  int m, const float *alpha, const float *beta, const float2 *const *w, float2 *const *y, float2 *t,
+                  hipStream_t st, int *k_inc) {
+  cand = plan_candidate_ok(d, cand);
+  Shape sh = shape_of(d);
+  sh.rpw_mult = 1 << (cand / 4);
+  sh.fused = (cand / 2) % 2 ? 0 : 1;
+  PF_DISPATCH_V(d.n, cand % 2, Ops<NN, VV>::chain(sh, F2(sens), mask, x0, m, alpha, beta, w, y, t, st, k_inc));
+}
+
 void grad_poly_op(const pfista_desc &d, const pfista_c32 *sens, const uint8_t *mask, double inv_l,
                   const std::vector<double> &c, const float2 *pre_x, const float2 *pre_w, float2 *g,
                   float2 *out, void *ws, hipStream_t st, int *k_inc, int cand = 0) {
@@ -519,13 +529,7 @@ void grad_poly_op(const pfista_desc &d, const pfista_c32 *sens, const uint8_t *m
   const Layout L = layout(d);
   float2 *t = at<float2>(ws, L.t);
   const Chain ch = make_chain(inv_l, c, pre_x, pre_w, g, out);
-  cand = plan_candidate_ok(d, cand);
-  Shape sh = shape_of(d);
-  sh.rpw_mult = 1 << (cand / 4);
-  sh.fused = (cand / 2) % 2 ? 0 : 1;
-  if (ch.m > 0)
-    PF_DISPATCH_V(d.n, cand % 2, Ops<NN, VV>::chain(sh, F2(sens), mask, ch.x0, ch.m, ch.alpha, ch.beta, ch.w, ch.y,
-                                                    t, st, k_inc));
+  if (ch.m > 0) chain_shaped(d, cand, sens, mask, ch.x0, ch.m, ch.alpha, ch.beta, ch.w, ch.y, t, st, k_inc);
   if (deg == 0 && !pre_x) pf::k_scale<<<blocks_for(L.n_img), 256, 0, st>>>(g, out, L.n_img, (float)c[0]);
 }
 
@@ -1724,6 +1728,8 @@ int check_unroll(const pfista_unroll_params *prm, std::vector<double> &c) {
   if (prm->ckpt_every < 1) return fail(PFISTA_EINVAL, "ckpt_every must be >= 1");
   if (!(prm->lambda >= 0.0) || !std::isfinite(prm->lambda)) return fail(PFISTA_EINVAL, "lambda must be finite and >= 0");
   if (!(prm->inv_l > 0.0) || !std::isfinite(prm->inv_l)) return fail(PFISTA_EINVAL, "inv_l must be finite and > 0");
+  if (prm->tune < -1 || prm->tune > PFISTA_TUNE_CANDIDATES)
+    return fail(PFISTA_EINVAL, "tune outside -1..%d", PFISTA_TUNE_CANDIDATES);
   if (prm->coef) {
     if (prm->degree < 0 || prm->degree > kMaxDegree) return fail(PFISTA_UNSUPPORTED, "degree %d", prm->degree);
     c.assign(prm->coef, prm->coef + prm->degree + 1);
@@ -1765,14 +1771,29 @@ size_t ckpt_bytes(const pfista_desc &d, const ULayout &U) {
 }
 
 
+// launch shape of the unrolled passes: params.tune as in pfista_params (the tuner
+// times chains from the image `x0` into the scratch images g, pg)
+int unroll_candidate(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *mask, const std::vector<double> &c,
+                     double inv_l, int tune, const float2 *x0, float2 *g, float2 *pg, void *ws, hipStream_t st,
+                     int &cand) {
+  cand = 0;
+  if (tune >= 1) {
+    cand = plan_candidate_ok(p->d, tune - 1);
+  } else if (tune == -1 && p->d.mask_kind == PFISTA_MASK_2D) {
+    double us = 0.0;
+    PF_TRY(tune_plan(p, sens, mask, c, inv_l, x0, g, pg, ws, st, cand, us));
+  }
+  return PFISTA_OK;
+}
+
 // One forward step of Algorithm 4 from (x, z): writes g and pg, then x, z.
 void unroll_step(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *mask, const std::vector<double> &c,
                  double inv_l, float lam, int use_k, const float2 *a, float2 *x, float2 *z, float2 *g, float2 *pg,
-                 void *ws, hipStream_t st) {
+                 void *ws, hipStream_t st, int cand) {
   const Layout L = layout(p->d);
   DevState *ds = at<DevState>(ws, L.state);
   const int deg = (int)c.size() - 1;
-  grad_poly_op(p->d, sens, mask, inv_l, c, z, a, g, pg, ws, st, &ds->k);
+  grad_poly_op(p->d, sens, mask, inv_l, c, z, a, g, pg, ws, st, &ds->k, cand);
   if (deg == 0) pf::k_scale<<<blocks_for(L.n_img), 256, 0, st>>>(g, pg, L.n_img, (float)c[0]);
   PF_DISPATCH(p->d.n, Ops<NN>::step(shape_of(p->d), z, pg, x, x, z, 1.f, lam, 0.f, &ds->k, use_k,
                                     at<double>(ws, L.partials), st));
@@ -1833,6 +1854,9 @@ int pfista_unroll_forward(const pfista_plan *p, const pfista_c32 *sens, const ui
   PF_DISPATCH(p->d.n, Ops<NN>::adjoint(shape_of(p->d), F2(sens), mask, F2(b), a,
                                        bnorm > 0.0 ? (float)(std::sqrt(il) / bnorm) : 0.f, at<float2>(ws, U.base.t),
                                        stream));
+  int cand = 0;
+  PF_TRY(unroll_candidate(p, sens, mask, c, il, prm->tune, a, at<float2>(ws, U.base.img[1]),
+                          at<float2>(ws, U.base.img[2]), ws, stream, cand));
   pf::k_fill<<<blocks_for(n), 256, 0, stream>>>(x, n, make_float2(0.f, 0.f));
   pf::k_fill<<<blocks_for(n), 256, 0, stream>>>(z, n, make_float2(0.f, 0.f));
   set_counter(ds, -1, stream);
@@ -1844,7 +1868,7 @@ int pfista_unroll_forward(const pfista_plan *p, const pfista_c32 *sens, const ui
       PF_HIP(hipMemcpyAsync(slot + n, z, n * sizeof(float2), hipMemcpyDeviceToDevice, stream));
     }
     unroll_step(p, sens, mask, c, il, (float)prm->lambda, use_k, a, x, z, at<float2>(ws, U.base.img[1]),
-                at<float2>(ws, U.base.img[2]), ws, stream);
+                at<float2>(ws, U.base.img[2]), ws, stream, cand);
   }
   PF_HIP(hipMemcpyAsync(x_out, x, n * sizeof(float2), hipMemcpyDeviceToDevice, stream));
   return launch_status("pfista_unroll_forward");
@@ -1882,6 +1906,9 @@ int pfista_unroll_backward(const pfista_plan *p, const pfista_c32 *sens, const u
   const double il = prm->inv_l;
   const float lam = (float)prm->lambda;
   const int use_k = prm->momentum ? 1 : 0;
+  int cand = 0;
+  PF_TRY(unroll_candidate(p, sens, mask, c, il, prm->tune, a, at<float2>(ws, U.base.img[1]),
+                          at<float2>(ws, U.base.img[2]), ws, stream, cand));
   PF_HIP(hipMemsetAsync(gdev, 0, (size_t)(deg + 2) * sizeof(double), stream));
   PF_HIP(hipMemcpyAsync(xb, x_bar, n * sizeof(float2), hipMemcpyDeviceToDevice, stream));
   pf::k_fill<<<blocks_for(n), 256, 0, stream>>>(zb, n, make_float2(0.f, 0.f));
@@ -1907,7 +1934,7 @@ int pfista_unroll_backward(const pfista_plan *p, const pfista_c32 *sens, const u
     for (int k = k0; k < k1; ++k) {
       float2 *sz = seg + (size_t)(3 * (k - k0)) * n;
       PF_HIP(hipMemcpyAsync(sz, z, n * sizeof(float2), hipMemcpyDeviceToDevice, stream));
-      unroll_step(p, sens, mask, c, il, lam, use_k, a, x, z, sz + n, sz + 2 * n, ws, stream);
+      unroll_step(p, sens, mask, c, il, lam, use_k, a, x, z, sz + n, sz + 2 * n, ws, stream, cand);
     }
     // pull back through the segment's steps in reverse order
     for (int k = k1 - 1; k >= k0; --k) {
@@ -1921,8 +1948,8 @@ int pfista_unroll_backward(const pfista_plan *p, const pfista_c32 *sens, const u
       }
       pf::k_reduce_add<<<1, 64, 0, stream>>>(partials, nsb, 1, 1.0, gdev);
       if (deg > 0)
-        PF_DISPATCH(d.n, Ops<NN>::chain(shape_of(d), F2(sens), mask, qb, deg, alpha, beta0, wnull, qy,
-                                        at<float2>(ws, U.base.t), stream, nullptr));
+        chain_shaped(d, cand, sens, mask, qb, deg, alpha, beta0, wnull, qy, at<float2>(ws, U.base.t), stream,
+                     nullptr);
       pf::k_poly_combine_dot<<<U.ncomb, 256, 0, stream>>>(qb, deg + 1, n, sz + n, carg, pv, cpart);
       pf::k_reduce_add<<<1, 64, 0, stream>>>(cpart, U.ncomb, deg + 1, -1.0, gdev + 1);
       // z_bar_k = v_bar - N' p(N') v_bar

@@ -37,10 +37,10 @@ def w1():
     return problem(1)
 
 
-def gpu_unrolled(inp, degree, iters, inv_l, ckpt_every=5, momentum=True):
+def gpu_unrolled(inp, degree, iters, inv_l, ckpt_every=5, momentum=True, tune=0):
     import paper_2204_10252_amd as pf
     plan = pf.Plan(inp["n"], inp["coils"], inp["slices"], haar_levels=inp["levels"])
-    return pf.Unrolled(plan, degree, iters, inv_l, ckpt_every=ckpt_every, momentum=momentum)
+    return pf.Unrolled(plan, degree, iters, inv_l, ckpt_every=ckpt_every, momentum=momentum, tune=tune)
 
 
 def smooth_lambda(inp, s128, bn, inv_l, coef, levels, K, momentum=True, lam0=None):
@@ -113,6 +113,27 @@ def test_gradient_every_haar_depth(w1, levels):
     close(np.concatenate([[gl], gc]), np.concatenate([[ol], oc]))
 
 
+@pytest.mark.parametrize("tune", [2, 6, 12, -1])
+def test_gradient_in_other_launch_shapes(w1, tune):
+    # forced candidates (second radix schedule, separate row passes, larger
+    # coil-combine blocks) and the tuned one give the same iterate and gradient
+    import torch
+    inp, sens, s128, b, bn, inv_l = w1
+    K, coef = 8, coefs(3)
+    lam = smooth_lambda(inp, s128, bn, inv_l, coef, inp["levels"], K)
+    u = gpu_unrolled(inp, 3, K, inv_l, tune=tune)
+    ts, tm, tb = to_dev(sens), to_dev(inp["mask"]), to_dev(b)
+    x = torch.empty((1, inp["n"], inp["n"]), dtype=torch.complex64, device="cuda")
+    u.forward(ts, tm, tb, x, lam, coef)
+    xo, _ = orc.unrolled_forward(s128, inp["mask"], bn, inv_l, lam, coef, inp["levels"], K)
+    assert rel(x.cpu().numpy(), xo) <= 1e-4
+    rng = np.random.default_rng(40)
+    xbar = c64(rng.standard_normal(xo.shape) + 1j * rng.standard_normal(xo.shape))
+    gl, gc = u.backward(ts, tm, to_dev(xbar), lam, coef)
+    ol, oc = orc.unrolled_vjp(s128, inp["mask"], bn, inv_l, lam, coef, inp["levels"], K, xbar.astype(np.complex128))
+    close(np.concatenate([[gl], gc]), np.concatenate([[ol], oc]))
+
+
 def test_checkpoint_interval_does_not_change_the_gradient(w1):
     import torch
     inp, sens, s128, b, bn, inv_l = w1
@@ -164,6 +185,8 @@ def test_unrolled_rejects_bad_parameters(w1):
         gpu_unrolled(inp, 2, 0, inv_l)
     with pytest.raises(pf.PfistaError):
         gpu_unrolled(inp, 2, 5, 0.0)
+    with pytest.raises(pf.PfistaError):
+        gpu_unrolled(inp, 2, 5, inv_l, tune=13)
 
 
 def test_workload5_full_size():
