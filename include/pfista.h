@@ -29,6 +29,10 @@
  * device workspace of at least pfista_workspace_bytes() bytes; the library
  * allocates no device memory and keeps no state between calls.
  *
+ * Devices: a plan or batch belongs to the device that is current when it is
+ * created; every call that takes it must run with that device current (EINVAL
+ * otherwise), with arrays and stream on that device.
+ *
  * Streams: every call enqueues on `stream` and returns without waiting, except
  * pfista_solve, pfista_data_term and pfista_power_iteration, which wait for
  * their host-visible scalars (documented per call).  Calls sharing a

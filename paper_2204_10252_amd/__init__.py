@@ -175,6 +175,9 @@ def _ptr(t, name, dtype=None, numel=None, allow_none=False):
     import torch
     if not t.is_cuda:
         raise ValueError(f"{name} must be a device tensor")
+    # the library launches on the current device (which must be the plan's)
+    if t.device.index != torch.cuda.current_device():
+        raise ValueError(f"{name} is on {t.device}, but the current device is cuda:{torch.cuda.current_device()}")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
     if dtype is not None and t.dtype != dtype:
@@ -187,6 +190,8 @@ def _ptr(t, name, dtype=None, numel=None, allow_none=False):
 def _stream(stream=None):
     import torch
     s = torch.cuda.current_stream() if stream is None else stream
+    if s.device.index != torch.cuda.current_device():
+        raise ValueError(f"stream is on {s.device}, but the current device is cuda:{torch.cuda.current_device()}")
     return ctypes.c_void_p(s.cuda_stream)
 
 

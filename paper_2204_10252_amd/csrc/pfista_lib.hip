@@ -164,9 +164,17 @@ Layout layout(const pfista_desc &d) {
 template <class T> T *at(void *ws, size_t off) { return reinterpret_cast<T *>(static_cast<char *>(ws) + off); }
 
 // ------------------------------------------------------------------ validation
+// a plan (or batch) belongs to the device that was current when it was created
+int check_device(int dev) {
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return fail(PFISTA_EHIP, "hipGetDevice failed");
+  if (cur != dev) return fail(PFISTA_EINVAL, "created on device %d, but device %d is current", dev, cur);
+  return PFISTA_OK;
+}
+
 int check_plan(const pfista_plan *p) {
   if (!p) return fail(PFISTA_EINVAL, "plan is NULL");
-  return PFISTA_OK;
+  return check_device(p->device);
 }
 
 int check_ptr(const void *ptr, const char *name, size_t align = 8) {
@@ -1446,6 +1454,7 @@ int pfista_batch_solve(const pfista_batch *b, const pfista_c32 *const *sens, con
                        const pfista_batch_params *prm, pfista_c32 *const *x_out, pfista_slice_report *slice_rep,
                        pfista_group_report *group_rep, pfista_batch_report *rep, void *ws, hipStream_t stream) {
   if (!b) return fail(PFISTA_EINVAL, "batch is NULL");
+  PF_TRY(check_device(b->device));
   std::vector<double> c;
   PF_TRY(check_batch_params(prm, c));
   const int count = (int)b->sl.size();

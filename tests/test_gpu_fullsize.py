@@ -56,3 +56,53 @@ def test_workload3_slab_sampled_slices():
     for s, (sens, mask, xs) in keep.items():
         ref = orc.normal(sens[None].astype(np.complex128), mask[None], xs[None].astype(np.complex128))
         assert rel(got[s], ref[0]) <= 1e-5, f"slice {s}"
+
+
+@pytest.mark.parametrize("slices,coils,kind", [(4369, 15, "2d"), (65535, 1, "2d"), (65535, 1, "1d")])
+def test_maximum_coil_images(slices, coils, kind):
+    """About 9 GB of device memory at the largest case."""
+    # slices * coils at the plan limit (65535 coil images, the largest second
+    # grid dimension of the column pass and of the phase-encode kernel): a few
+    # distinct 64 x 64 cases tiled over all slices; sampled slices against the
+    # oracle, and the fused step over every slice against its formula
+    import torch
+    import paper_2204_10252_amd as pf
+    from tests.gpu_util import random_case
+    n, base = 64, 5
+    sens, mask, x, w = random_case(n, coils, base, kind, seed=900 + coils)
+    reps = -(-slices // base)
+    ts = to_dev(sens).repeat(reps, 1, 1, 1)[:slices].contiguous()
+    tm = to_dev(mask).repeat((reps,) + (1,) * (mask.ndim - 1))[:slices].contiguous()
+    tx = to_dev(x).repeat(reps, 1, 1)[:slices].contiguous()
+    plan = pf.Plan(n, coils, slices, haar_levels=4, mask_kind=pf.MASK_1D if kind == "1d" else pf.MASK_2D)
+    ty = torch.empty_like(tx)
+    pf.normal_apply(plan, ts, tm, tx, ty, 1.0)
+    for s in (0, slices // 2, slices - 1):
+        b = s % base
+        ref = orc.normal(sens[b:b + 1].astype(np.complex128), mask[b:b + 1], x[b:b + 1].astype(np.complex128))
+        assert rel(ty[s].cpu().numpy(), ref[0]) <= 1e-5, f"slice {s}"
+    del ts
+    # the step over every slice: z = x, pg = y, x_old = w (tiled the same way)
+    to = to_dev(w).repeat(reps, 1, 1)[:slices].contiguous()
+    xn, zn = torch.empty_like(tx), torch.empty_like(tx)
+    red = torch.zeros(3, dtype=torch.float64, device=tx.device)
+    lam, beta = 0.2, 0.5
+    pf.step(plan, tx, ty, to, xn, zn, lam, beta, red)
+    pgs = ty[:base].cpu().numpy().astype(np.complex128)
+    l1 = dx2 = xn2 = 0.0
+    for b in range(base):
+        rx, rz = orc.pfista_step(x[b:b + 1].astype(np.complex128), pgs[b:b + 1], w[b:b + 1].astype(np.complex128),
+                                 lam, 4, beta)
+        for s in range(b, slices, base * 4099):
+            assert rel(xn[s].cpu().numpy(), rx[0]) <= 1e-5, f"slice {s}"
+            assert rel(zn[s].cpu().numpy(), rz[0]) <= 1e-5, f"slice {s}"
+        cnt = len(range(b, slices, base))
+        l1 += cnt * np.sum(np.abs(orc.haar_fwd(rx, 4)))
+        dx2 += cnt * np.linalg.norm(rx - w[b:b + 1]) ** 2
+        xn2 += cnt * np.linalg.norm(rx) ** 2
+    r = red.cpu().numpy()
+    # the tiled slices repeat exactly, so the whole-batch sums are multiples of the
+    # per-case sums (the pg of equal cases is equal: the apply is per slice)
+    assert r[0] == pytest.approx(l1, rel=1e-5)
+    assert r[1] == pytest.approx(dx2, rel=1e-5)
+    assert r[2] == pytest.approx(xn2, rel=1e-5)
