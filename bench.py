@@ -528,6 +528,21 @@ def cpu_oracle_applies(seconds_each=1.0):
                     k += 1
                 res[key] = round(1e3 * (time.perf_counter() - t0) / k, 3)
         out[label] = res
+    # the slab is 32 independent slices: its oracle apply is 32 x the one-slice time
+    one = out["384x384x32_phase_encode"]
+    out["384x384x32_phase_encode"].update(
+        {"slab_32_slices_one_thread_ms_extrapolated": round(32 * one["one_thread_ms"], 1),
+         "slab_32_slices_all_cores_ms_extrapolated": round(32 * one["all_cores_ms"], 1)})
+    # a whole solve of the small workload (50 PFISTA iterations, d = 3), measured
+    from synth import make_inputs
+    w1 = make_inputs(1)
+    s1 = w1["sens"].astype(np.complex64).astype(np.complex128)
+    b1 = orc.kspace_data(s1, w1["mask"], w1["phantom"], w1["noise"])
+    with scipy.fft.set_workers(1):
+        t0 = time.perf_counter()
+        orc.pfista(s1, w1["mask"], b1 / np.linalg.norm(b1), 1.0 / 1.01, w1["lam"], orc.l2_poly_coefficients(3),
+                   w1["levels"], 50)
+        out["64x64x4"]["pfista_50_iterations_d3_one_thread_ms"] = round(1e3 * (time.perf_counter() - t0), 1)
     return out
 
 
@@ -555,7 +570,8 @@ def cpu_baseline(inp, degree, seconds):
     return {"value": round(k * (degree + 1) / dt, 3), "unit": "A^H A applies/s", "cores": 1, "kind": "oracle",
             "host_cores_available": avail,
             "sample": f"{k} PFISTA iterations (degree {degree}, {k * (degree + 1)} applies) of the "
-                      f"256x256 16-coil workload in {dt:.1f} s, complex128 NumPy/SciPy, one thread"}
+                      f"256x256 16-coil workload in {dt:.1f} s, complex128 NumPy/SciPy, one thread",
+            "full_200_iteration_solve_s_extrapolated": round(200 * dt / k, 1)}
 
 
 def main():
