@@ -4,8 +4,11 @@
   oracle (it finishes in well under a second at this size).
 * slab of 32 slices 384 x 384, 32 coils, phase-encode mask: the GPU applies the
   operator to all 32 slices at once; the oracle recomputes three sampled
-  slices (slices are independent blocks of A).
-Bar: relative l2 error <= 1e-5 per checked slice.
+  slices (slices are independent blocks of A); likewise 8 PFISTA iterations
+  (d = 4) of the whole slab against the oracle on two slices.
+* the plan's limit of 65535 coil images.
+Bar: relative l2 error <= 1e-5 per checked slice for applies and steps, 1e-4 for
+iterates.
 """
 
 import numpy as np
@@ -106,3 +109,40 @@ def test_maximum_coil_images(slices, coils, kind):
     assert r[0] == pytest.approx(l1, rel=1e-5)
     assert r[1] == pytest.approx(dx2, rel=1e-5)
     assert r[2] == pytest.approx(xn2, rel=1e-5)
+
+
+def test_workload3_slab_solve_sampled_slices():
+    # PFISTA (d = 4) on the whole 32-slice slab with one global normalisation; the
+    # slab is block diagonal, so slice s follows the oracle's iteration on slice s
+    # alone given the same scalars (||b|| of the slab, 1/L, the shared momentum)
+    import torch
+    import paper_2204_10252_amd as pf
+    n, coils, slices, K = 384, 32, 32, 8
+    dev = torch.device("cuda", 0)
+    ts = torch.empty((slices, coils, n, n), dtype=torch.complex64, device=dev)
+    tm = torch.empty((slices, n), dtype=torch.uint8, device=dev)
+    tb = torch.empty((slices, coils, n, n), dtype=torch.complex64, device=dev)
+    keep, bn2 = {}, 0.0
+    for s in range(slices):
+        d = make_slice_inputs(3, s)
+        sens = c64(d["sens"])
+        b = c64(orc.kspace_data(sens[None].astype(np.complex128), d["mask"][None], d["phantom"][None],
+                                d["noise"][None]))[0]
+        bn2 += float(np.sum(np.abs(b.astype(np.complex128)) ** 2))
+        ts[s].copy_(torch.from_numpy(sens))
+        tm[s].copy_(torch.from_numpy(d["mask"]))
+        tb[s].copy_(torch.from_numpy(b))
+        if s in (0, 31):
+            keep[s] = (sens, d["mask"], b, d["lam"])
+    inv_l = 1.0 / 1.01           # ||A||^2 <= 1 for root-sum-of-squares normalised maps
+    coef = [float(c) for c in orc.l2_poly_coefficients(4)]
+    plan = pf.Plan(n, coils, slices, haar_levels=4, mask_kind=pf.MASK_1D)
+    x = torch.empty((slices, n, n), dtype=torch.complex64, device=dev)
+    lam = keep[0][3]
+    rep = pf.solve(plan, ts, tm, tb, x, lam, coef=coef, max_iter=K, inv_l=inv_l)
+    assert rep["bnorm"] == pytest.approx(np.sqrt(bn2), rel=1e-6)
+    del ts, tb
+    for s, (sens, mask, b, _) in keep.items():
+        bn = b[None].astype(np.complex128) / np.sqrt(bn2)
+        xo, _, _ = orc.pfista(sens[None].astype(np.complex128), mask[None], bn, inv_l, lam, coef, 4, K)
+        assert rel(x[s].cpu().numpy(), xo[0]) <= 1e-4, f"slice {s}"
