@@ -748,7 +748,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "fp32 (complex64), fp64 reductions",
+        "dtype": "f32",
+        "dtype_detail": "complex64 data, FP32 arithmetic, FP64 reductions",
         "data": "synthetic (seeded phantom, coil maps, Poisson-disc-like mask, noise)",
         "config": {"workload": "Cartesian SENSE 256x256, 16 coils, R=6, 4-level Haar, lambda=5e-4",
                    "degree": d, "step": f"1 PFISTA iteration = {d + 1} A^H A applies + prox/momentum",
