@@ -278,3 +278,41 @@ def test_converged_objective_matches_oracle(c1, degree, iters):
     assert rep["objective"] == pytest.approx(hist[-1], rel=1e-6)
     # and it is converged: the last 10 % of the iterations moved F by less than 1e-6
     assert abs(hist[-1] - hist[int(0.9 * iters)]) <= 1e-6 * hist[-1]
+
+
+def test_concurrent_solves_from_two_host_threads(c1):
+    # two plans solved at once from two host threads on their own streams (the
+    # library keeps no shared mutable state besides its locked tuner cache and
+    # per-thread error messages); each result equals the same solve run alone
+    import threading
+    import torch
+    import paper_2204_10252_amd as pf
+    inp, sens, s128, b, bn, inv_l = c1
+    args = (to_dev(sens), to_dev(inp["mask"]), to_dev(b))
+    coef = [float(c) for c in orc.l2_poly_coefficients(3)]
+
+    def run(plan, x, stream, tune, out):
+        with torch.cuda.stream(stream):
+            out.append(pf.solve(plan, *args, x, inp["lam"], coef=coef, max_iter=40, inv_l=inv_l, graph_iters=5,
+                                check_every=20, tune=tune, stream=stream))
+        stream.synchronize()
+
+    ref = []
+    for tune in (0, -1):
+        x = torch.empty((1, inp["n"], inp["n"]), dtype=torch.complex64, device="cuda")
+        run(gpu_plan(inp), x, torch.cuda.Stream(), tune, [])
+        ref.append(x.clone())
+    plans = [gpu_plan(inp), gpu_plan(inp)]
+    xs = [torch.empty((1, inp["n"], inp["n"]), dtype=torch.complex64, device="cuda") for _ in plans]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs = [[], []]
+    torch.cuda.synchronize()
+    threads = [threading.Thread(target=run, args=(plans[i], xs[i], streams[i], (0, -1)[i], outs[i]))
+               for i in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert all(len(o) == 1 and o[0]["rc"] == pf.OK for o in outs)
+    for i in range(2):
+        assert torch.equal(xs[i], ref[i])
