@@ -1483,9 +1483,7 @@ int pfista_batch_solve(const pfista_batch *b, const pfista_c32 *const *sens, con
     need_power = need_power || il == 0.0;
   }
   if (need_power && prm->power_iters < 1) return fail(PFISTA_EINVAL, "estimating inv_l needs power_iters >= 1");
-  int dev = 0;
-  PF_HIP(hipGetDevice(&dev));
-  if (dev != b->device) return fail(PFISTA_EINVAL, "batch was created on device %d, current is %d", b->device, dev);
+  const int dev = b->device;   // current (checked above)
   const int deg = (int)c.size() - 1;
   const int ng = (int)b->g.size();
 
