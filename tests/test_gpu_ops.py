@@ -199,3 +199,21 @@ def test_validation_errors():
     pf.normal_apply(p0, torch.empty((0, 2, 64, 64), dtype=torch.complex64, device=tx.device),
                     torch.empty((0, 64, 64), dtype=torch.uint8, device=tx.device), empty,
                     torch.empty_like(empty))
+
+
+@pytest.mark.parametrize("n,coils,slices,kind", [(384, 3, 2, "1d"), (160, 2, 3, "2d"), (512, 1, 1, "1d")])
+def test_data_term_and_power_iteration_other_shapes(n, coils, slices, kind):
+    # the residual column pass of phase-encode masks and of several slices
+    import paper_2204_10252_amd as pf
+    sens, mask, x, _ = random_case(n, coils, slices, kind, seed=n + slices)
+    plan = _plan(n, coils, slices, kind)
+    ts, tm = to_dev(sens), to_dev(mask)
+    rng = np.random.default_rng(2)
+    b = c64(orc.forward(sens.astype(complex), mask, rng.standard_normal((slices, n, n)) + 0j))
+    dt = pf.data_term(plan, ts, tm, to_dev(b), to_dev(x), 0.7, 0.5)
+    r = np.sqrt(0.7) * orc.forward(sens.astype(complex), mask, x.astype(complex)) - 0.5 * b
+    assert dt == pytest.approx(0.5 * np.vdot(r, r).real, rel=1e-5)
+    v0 = c64(rng.standard_normal((slices, n, n)) + 1j * rng.standard_normal((slices, n, n)))
+    lam = pf.power_iteration(plan, ts, tm, 20, v=to_dev(v0))
+    ref = orc.power_iteration(sens.astype(np.complex128), mask, v0.astype(np.complex128), 20)
+    assert lam == pytest.approx(ref, rel=1e-5)
