@@ -185,8 +185,8 @@ int pfista_poly_coefficients_weighted(int degree, double alpha, double *coef);
 int pfista_poly_coefficients_chebyshev(int degree, double mu, double *coef);
 
 /* Launch-shape candidates of the normal-operator chain (2-D masks), which a
- * solve (pfista_params.tune) or a batch group (pfista_batch_params.tune) can be
- * forced to with tune = k + 1: candidate k uses radix schedule k % 2 (0:
+ * solve (pfista_params.tune), the unrolled passes (pfista_unroll_params.tune) or
+ * a batch group (pfista_batch_params.tune) can be forced to with tune = k + 1: candidate k uses radix schedule k % 2 (0:
  * default, 1: twice the lanes per transform), fuses the Horner row passes
  * unless (k / 2) % 2, and multiplies the rows per coil-combine block by
  * 2^(k / 4).  Every candidate computes the same operator. */
@@ -229,7 +229,8 @@ typedef struct {
   double bnorm;           /* ||b|| */
   long long normal_applies; /* A^H A applications in the loop */
   int candidate;          /* launch shape used */
-  double tune_us;         /* tuner's time of one chain (0 if not timed) */
+  double tune_us;         /* with tune == -1: the tuned shape's time of one chain
+                             (measured now or read from the cache); else 0 */
 } pfista_report;
 
 /* Algorithm 4 on the caller's stream.  Setup (FP64 ||b||, optional power
