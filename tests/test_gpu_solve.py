@@ -316,3 +316,48 @@ def test_concurrent_solves_from_two_host_threads(c1):
     assert all(len(o) == 1 and o[0]["rc"] == pf.OK for o in outs)
     for i in range(2):
         assert torch.equal(xs[i], ref[i])
+
+
+_CACHE_SCRIPT = r"""
+import sys
+sys.path.insert(0, sys.argv[1])
+import numpy as np, torch
+import paper_2204_10252_amd as pf
+from synth import make_inputs
+inp = make_inputs(1)
+dev = torch.device("cuda", 0)
+plan = pf.Plan(inp["n"], inp["coils"], 1, haar_levels=inp["levels"])
+sens = torch.from_numpy(inp["sens"].astype(np.complex64)).to(dev)
+mask = torch.from_numpy(inp["mask"]).to(dev)
+b = torch.empty((1, inp["coils"], inp["n"], inp["n"]), dtype=torch.complex64, device=dev)
+pf.forward(plan, sens, mask, torch.from_numpy(inp["phantom"].astype(np.complex64)).to(dev), b)
+x = torch.empty((1, inp["n"], inp["n"]), dtype=torch.complex64, device=dev)
+rep = pf.solve(plan, sens, mask, b, x, inp["lam"], degree=3, max_iter=3, inv_l=0.9, tune=-1)
+print("CANDIDATE", rep["candidate"], rep["tune_us"])
+"""
+
+
+def test_tuner_cache_file(tmp_path):
+    # a tuned solve writes its choice to $PFISTA_TUNE_CACHE; a later process reads
+    # it back (here an entry edited to candidate 6) instead of timing again
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    cache = tmp_path / "tune.txt"
+    env = dict(os.environ, PFISTA_TUNE_CACHE=str(cache))
+
+    def run():
+        out = subprocess.run([sys.executable, "-c", _CACHE_SCRIPT, root], env=env, capture_output=True,
+                             text=True, timeout=240)
+        assert out.returncode == 0, out.stderr[-2000:]
+        line = [ln for ln in out.stdout.splitlines() if ln.startswith("CANDIDATE")][-1].split()
+        return int(line[1]), float(line[2])
+
+    cand, us = run()
+    lines = cache.read_text().split("\n")
+    entry = [ln for ln in lines if "|plan|n64|s1|c4|" in ln]
+    assert len(entry) == 1 and int(entry[0].split()[1]) == cand and us > 0
+    key = entry[0].split()[0]
+    cache.write_text(f"{key} 6 12.5\n")
+    assert run() == (6, 12.5)
