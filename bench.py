@@ -169,7 +169,7 @@ def cold_warm_apply(torch, pf, plan, sens, mask, x, y, stream, reps=20, flush_mb
 
 
 def time_to_tolerance(torch, pf, plan, sens, mask, b, lam, inv_l, stream, graph_iters,
-                      obj_tols=(1e-4, 1e-6), it_tols=(1e-2, 1e-3), ref_applies=6000,
+                      obj_tols=(1e-4, 1e-6), it_tols=(1e-2, 1e-3, 1e-4), ref_applies=6000,
                       max_hist_applies=2400, degrees=(1, 2, 3, 4, 5), iterate=True, reps=11):
     """Iterations and GPU time for each method to reach each tolerance."""
     out = {}
