@@ -20,10 +20,11 @@ iterations (inputs resident in HBM, graph-replayed loop).  Also reported:
 * the slab workload (32 slices 384 x 384, 32 coils, phase-encode mask): the
   HBM-streaming normal operator and a degree-4 PFISTA iteration;
 * the batch workload (64 uneven slices): the batched solver's loop time with
-  tuned and default launch shapes, 1 and 4 concurrent branches, against
+  tuned and default launch shapes, 1, 2 and 4 concurrent branches, against
   solving the slices one plan at a time;
 * the differentiation workload (8 slices 192 x 192, 12 coils, 20 unrolled
-  degree-4 iterations): forward and hand-written backward pass times;
+  degree-4 iterations): forward and hand-written backward pass times, in the
+  default and in the tuned launch shape;
 * the non-Cartesian workload (256 x 256, 12 coils, spiral): the Toeplitz
   normal operator and a degree-3 PFISTA iteration;
 * the FP64 oracle timed on the host cores on a bounded sample (cpu_baseline).
