@@ -10,6 +10,7 @@ file (``python -m paper_2204_10252_amd.build``); there is no fallback.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import re
 
@@ -18,7 +19,7 @@ __all__ = [
     "poly_coefficients_weighted", "poly_coefficients_chebyshev", "normal_apply", "poly_apply", "step", "forward", "adjoint", "data_term",
     "power_iteration", "profile_normal", "solve", "MASK_2D", "MASK_1D", "TOEPLITZ", "header_functions",
     "toeplitz_kernel", "nudft_forward", "nudft_adjoint",
-    "Batch", "batch_solve", "TUNE_CANDIDATES", "Unrolled", "unrolled_pfista",
+    "Batch", "batch_solve", "TUNE_CANDIDATES", "Unrolled", "unrolled_pfista", "image_scale",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -387,6 +388,14 @@ def solve(plan, sens, mask, b, x, lam, degree=3, coef=None, max_iter=50, inv_l=0
         _check(rc)
     out["rc"] = rc
     return out
+
+
+def image_scale(report) -> float:
+    """Factor that takes a solution from the normalised problem (A' = sqrt(inv_l) A,
+    b' = b / ||b||) back to the units of the data: x = image_scale(rep) * x'.
+    ``report``: the dict of ``solve`` or one entry of ``batch_solve``'s
+    ``slices``."""
+    return math.sqrt(float(report["inv_l"])) * float(report["bnorm"])
 
 
 # ------------------------------------------------------------------ batches

@@ -161,3 +161,18 @@ def test_binding_structs_match_the_header_layout(tmp_path):
         assert ctypes.sizeof(cls) == c[(s, "size")], s
         for (n, _), f in zip(cls._fields_, fields[s]):
             assert getattr(cls, n).offset == c[(s, f)], (s, f)
+
+
+def test_image_scale_undoes_the_normalisation():
+    # A' = sqrt(inv_l) A and b' = b/||b||: if A' x' = b' then A (s x') = b with
+    # s = sqrt(inv_l) ||b||; checked on a dense random A
+    import numpy as np
+    import paper_2204_10252_amd as pf
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((12, 5))
+    x = rng.standard_normal(5)
+    b = A @ x
+    inv_l = 0.37
+    xp = np.linalg.lstsq(np.sqrt(inv_l) * A, b / np.linalg.norm(b), rcond=None)[0]
+    s = pf.image_scale({"inv_l": inv_l, "bnorm": float(np.linalg.norm(b))})
+    assert np.allclose(s * xp, x, rtol=1e-12, atol=1e-12)
