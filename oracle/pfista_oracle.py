@@ -33,6 +33,7 @@ __all__ = [
     "haar_fwd", "haar_inv", "soft_threshold", "prox_l1_haar", "objective",
     "data_term", "power_iteration", "pfista", "pfista_step", "normalise",
     "chebyshev_poly_coefficients", "weighted_l2_poly_coefficients", "pgd",
+    "momentum_beta", "horner", "iterate",
 ]
 
 _SQRT_HALF = np.sqrt(0.5)
@@ -200,15 +201,20 @@ def poly_eval(coef, z):
     return out
 
 
-def poly_apply(sens: np.ndarray, mask: np.ndarray, scale: float, coef, g: np.ndarray) -> np.ndarray:
-    """``p(N') g`` with ``N' = scale * A^H A``, nested as in Listing 1:
-    ``P = c0 I + N'(c1 I + N'(c2 I + ...))``, i.e. ``h = c_d g`` then
-    ``h = c_i g + N' h`` for ``i = d-1, ..., 0`` (d applications of N')."""
+def horner(apply, coef, g: np.ndarray) -> np.ndarray:
+    """``p(N') g`` for a normal operator given as the function ``apply``, nested
+    as in Listing 1: ``P = c0 I + N'(c1 I + N'(c2 I + ...))``, i.e. ``h = c_d g``
+    then ``h = c_i g + N' h`` for ``i = d-1, ..., 0`` (d applications of N')."""
     c = [float(v) for v in coef]
     h = c[-1] * g
     for ci in reversed(c[:-1]):
-        h = ci * g + normal(sens, mask, h, scale)
+        h = ci * g + apply(h)
     return h
+
+
+def poly_apply(sens: np.ndarray, mask: np.ndarray, scale: float, coef, g: np.ndarray) -> np.ndarray:
+    """``p(N') g`` with the Cartesian ``N' = scale * A^H A`` (``horner``)."""
+    return horner(lambda v: normal(sens, mask, v, scale), coef, g)
 
 
 # ----------------------------------------------------------------------------
@@ -291,43 +297,73 @@ def pfista_step(z, pg, x_old, lam, levels, beta):
     return x_new, z_new
 
 
+def momentum_beta(k: int) -> float:
+    """Momentum weight of step ``k >= 0`` in Algorithms 2 and 4:
+    ``beta_k = k / (k + 3)`` (0, 1/4, 2/5, 1/2, 4/7, ...)."""
+    return k / (k + 3.0)
+
+
+def iterate(apply, ahb, lam, coef, levels, iters, x0=None, z0=None, k0=0, momentum=True,
+            record=None):
+    """The iteration of Algorithm 4 for any normal operator ``apply`` (``N'``)
+    and data image ``ahb`` (``A'^H b'``); every solver of the oracle runs it.
+
+    Step k (from ``x_0 = z_0 = 0``, or the given state after ``k0`` steps):
+    ``g = N' z_k - A'^H b'``; ``x_{k+1} = prox(z_k - p(N') g)``;
+    ``z_{k+1} = x_{k+1} + beta_k (x_{k+1} - x_k)`` with ``beta_k = k/(k+3)``
+    (``momentum_beta``), or ``beta_k = 0`` without momentum (Algorithms 1 and 3,
+    where ``z = x``).  The momentum uses the newest iterate, the usual FISTA
+    form (the printed update names the older pair of iterates).
+
+    ``record(k, z_k, g, pg, beta_k, x_{k+1})`` is called after every step.
+    Returns ``(x, z)`` after the last step.
+    """
+    x = np.zeros_like(ahb) if x0 is None else np.array(x0, dtype=np.complex128)
+    z = np.zeros_like(ahb) if z0 is None else np.array(z0, dtype=np.complex128)
+    for k in range(k0, k0 + iters):
+        g = apply(z) - ahb
+        pg = horner(apply, coef, g)
+        beta = momentum_beta(k) if momentum else 0.0
+        x_new, z_new = pfista_step(z, pg, x, lam, levels, beta)
+        if record is not None:
+            record(k, z, g, pg, beta, x_new)
+        x, z = x_new, z_new
+    return x, z
+
+
 def pgd(sens, mask, bn, scale, lam, coef, levels, iters, x0=None, history=False):
     """Proximal gradient descent with the polynomial preconditioner: Algorithm 3
     (PPGD), or Algorithm 1 (PGD) when coef = [1]:
-    ``y_(k+1) = prox(y_k - p(N')(N' y_k - A'^H b'))`` from ``y_0 = 0``."""
+    ``y_(k+1) = prox(y_k - p(N')(N' y_k - A'^H b'))`` from ``y_0 = 0``
+    (``iterate`` without momentum)."""
     ahb = scale ** 0.5 * adjoint(sens, mask, bn)
-    y = np.zeros_like(ahb) if x0 is None else np.array(x0, dtype=np.complex128)
     hist = []
-    for _ in range(iters):
-        g = normal(sens, mask, y, scale) - ahb
-        y = prox_l1_haar(y - poly_apply(sens, mask, scale, coef, g), lam, levels)
+
+    def rec(k, z, g, pg, beta, x_new):
         if history:
-            hist.append(objective(sens, mask, bn, scale, y, lam, levels))
+            hist.append(objective(sens, mask, bn, scale, x_new, lam, levels))
+
+    y, _ = iterate(lambda v: normal(sens, mask, v, scale), ahb, lam, coef, levels, iters,
+                   x0=x0, z0=x0, momentum=False, record=rec)
     return y, hist
 
 
 def pfista(sens, mask, bn, scale, lam, coef, levels, iters, x0=None, z0=None, k0=0,
            history=False):
-    """Polynomial-preconditioned FISTA, Algorithm 4 (Algorithm 2 when coef = [1]).
-
-    With ``N' = scale A^H A`` and ``b' = bn`` (already normalised), step k >= 0:
-    ``g = N' z_k - A'^H b'``; ``x_{k+1} = prox(z_k - p(N') g)``;
-    ``beta_k = k / (k + 3)``; ``z_{k+1} = x_{k+1} + beta_k (x_{k+1} - x_k)``,
-    from ``x_0 = z_0 = 0``.  The momentum uses the newest iterate, the usual
-    FISTA form (the printed update names the older pair of iterates).
+    """Polynomial-preconditioned FISTA, Algorithm 4 (Algorithm 2 when coef = [1]),
+    with the Cartesian ``N' = scale A^H A`` and ``b' = bn`` (already normalised):
+    ``iterate`` from ``x_0 = z_0 = 0``.
 
     Returns ``(x, z, hist)``; ``hist`` holds ``F(x_{k+1})`` per step if asked.
     Passing ``x0, z0, k0`` resumes from the state after ``k0`` steps.
     """
     ahb = scale ** 0.5 * adjoint(sens, mask, bn)
-    x = np.zeros_like(ahb) if x0 is None else np.array(x0, dtype=np.complex128)
-    z = np.zeros_like(ahb) if z0 is None else np.array(z0, dtype=np.complex128)
     hist = []
-    for k in range(k0, k0 + iters):
-        g = normal(sens, mask, z, scale) - ahb
-        pg = poly_apply(sens, mask, scale, coef, g)
-        beta = k / (k + 3.0)
-        x, z = pfista_step(z, pg, x, lam, levels, beta)
+
+    def rec(k, z, g, pg, beta, x_new):
         if history:
-            hist.append(objective(sens, mask, bn, scale, x, lam, levels))
+            hist.append(objective(sens, mask, bn, scale, x_new, lam, levels))
+
+    x, z = iterate(lambda v: normal(sens, mask, v, scale), ahb, lam, coef, levels, iters,
+                   x0=x0, z0=z0, k0=k0, record=rec)
     return x, z, hist

@@ -22,7 +22,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .pfista_oracle import haar_fwd, prox_l1_haar
+from .pfista_oracle import haar_fwd, iterate
 
 __all__ = ["nudft_matrix", "nudft_forward", "nudft_adjoint", "nudft_normal", "toeplitz_kernel",
            "toeplitz_normal", "nc_data_term", "pfista_nc", "pfista_toeplitz"]
@@ -92,44 +92,23 @@ def nc_data_term(sens, traj, bn, scale, x) -> float:
 
 def pfista_nc(sens, traj, bn, scale, lam, coef, levels, iters, history=False):
     """Algorithm 4 with the non-Cartesian model ``A = E S`` (direct DFT sums):
-    the iteration of ``pfista`` with ``N' = scale A^H A``, ``a = sqrt(scale) A^H bn``."""
+    ``iterate`` with ``N' = scale A^H A`` and ``a = sqrt(scale) A^H bn``."""
     a = np.sqrt(scale) * nudft_adjoint(sens, traj, bn)
-    x = np.zeros_like(a)
-    z = np.zeros_like(a)
     hist = []
 
-    def nop(v):
-        return nudft_normal(sens, traj, v, scale)
-
-    for k in range(iters):
-        g = nop(z) - a
-        h = float(coef[-1]) * g
-        for ci in reversed([float(c) for c in coef[:-1]]):
-            h = ci * g + nop(h)
-        x_new = prox_l1_haar(z - h, lam, levels)
-        beta = k / (k + 3.0)
-        z = x_new + beta * (x_new - x)
-        x = x_new
+    def rec(k, z, g, pg, beta, x_new):
         if history:
-            hist.append(nc_data_term(sens, traj, bn, scale, x)
-                        + lam * float(np.sum(np.abs(haar_fwd(x, levels)))))
+            hist.append(nc_data_term(sens, traj, bn, scale, x_new)
+                        + lam * float(np.sum(np.abs(haar_fwd(x_new, levels)))))
+
+    x, z = iterate(lambda v: nudft_normal(sens, traj, v, scale), a, lam, coef, levels, iters, record=rec)
     return x, z, hist
 
 
 def pfista_toeplitz(sens, kern, ahb, bnorm, scale, lam, coef, levels, iters):
     """Algorithm 4 from ``A^H b`` and ``||b||`` alone (as a Toeplitz solver
-    receives its data): ``N' = scale T`` with the Toeplitz operator of ``kern``,
-    ``a = sqrt(scale) A^H b / ||b||``; the same iteration as ``pfista_nc``."""
+    receives its data): ``iterate`` with ``N' = scale T`` for the Toeplitz
+    operator T of ``kern`` and ``a = sqrt(scale) A^H b / ||b||``."""
     a = np.sqrt(scale) * ahb / bnorm
-    x = np.zeros_like(a)
-    z = np.zeros_like(a)
-    for k in range(iters):
-        g = toeplitz_normal(sens, kern, z, scale) - a
-        h = float(coef[-1]) * g
-        for ci in reversed([float(c) for c in coef[:-1]]):
-            h = ci * g + toeplitz_normal(sens, kern, h, scale)
-        x_new = prox_l1_haar(z - h, lam, levels)
-        beta = k / (k + 3.0)
-        z = x_new + beta * (x_new - x)
-        x = x_new
+    x, _ = iterate(lambda v: toeplitz_normal(sens, kern, v, scale), a, lam, coef, levels, iters)
     return x

@@ -29,7 +29,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .pfista_oracle import adjoint, haar_fwd, haar_inv, normal, poly_apply, soft_threshold
+from .pfista_oracle import adjoint, haar_fwd, haar_inv, iterate, normal
 
 __all__ = ["soft_threshold_vjp", "prox_l1_haar_vjp", "poly_vjp", "unrolled_forward", "unrolled_vjp"]
 
@@ -68,19 +68,12 @@ def poly_vjp(sens, mask, scale, coef, g, v_bar):
 
 
 def unrolled_forward(sens, mask, bn, scale, lam, coef, levels, iters, momentum=True):
-    """``x_K`` and the per-step ``(z_k, g_k, pg_k)`` of K steps from zero."""
+    """``x_K`` and the per-step ``(z_k, g_k, pg_k, beta_k)`` of K steps of
+    ``iterate`` from zero."""
     a = scale ** 0.5 * adjoint(sens, mask, bn)
-    x = np.zeros_like(a)
-    z = np.zeros_like(a)
     tape = []
-    for k in range(iters):
-        g = normal(sens, mask, z, scale) - a
-        pg = poly_apply(sens, mask, scale, coef, g)
-        x_new = haar_inv(soft_threshold(haar_fwd(z - pg, levels), lam), levels)
-        beta = k / (k + 3.0) if momentum else 0.0
-        tape.append((z, g, pg, beta))
-        z = x_new + beta * (x_new - x)
-        x = x_new
+    x, _ = iterate(lambda v: normal(sens, mask, v, scale), a, lam, coef, levels, iters, momentum=momentum,
+                   record=lambda k, z, g, pg, beta, x_new: tape.append((z, g, pg, beta)))
     return x, tape
 
 
