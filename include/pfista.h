@@ -231,6 +231,9 @@ typedef struct {
   int candidate;          /* launch shape used */
   double tune_us;         /* with tune == -1: the tuned shape's time of one chain
                              (measured now or read from the cache); else 0 */
+  double loop_ms;         /* device time of the iteration loop: HIP events on
+                             `stream` from before the first iteration to after
+                             the last check (set-up excluded); 0 if no iteration */
 } pfista_report;
 
 /* Algorithm 4 on the caller's stream.  Setup (FP64 ||b||, optional power

@@ -53,7 +53,7 @@ class _Report(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("status", ctypes.c_int), ("objective", ctypes.c_double),
                 ("rel_change", ctypes.c_double), ("l1", ctypes.c_double), ("inv_l", ctypes.c_double),
                 ("bnorm", ctypes.c_double), ("normal_applies", ctypes.c_longlong),
-                ("candidate", ctypes.c_int), ("tune_us", ctypes.c_double)]
+                ("candidate", ctypes.c_int), ("tune_us", ctypes.c_double), ("loop_ms", ctypes.c_double)]
 
 
 class _SliceDesc(ctypes.Structure):
@@ -492,8 +492,11 @@ def batch_solve(batch, sens, mask, b, x, lam, degree=3, coef=None, max_iter=50, 
 class Unrolled:
     """K unrolled iterations of Algorithm 4 on one plan, differentiable in the
     threshold and the polynomial coefficients (``pfista_unroll_forward`` /
-    ``pfista_unroll_backward``).  Holds the checkpoint buffer of the last
-    forward pass and the workspace.  ``tune``: launch shape as in ``solve``."""
+    ``pfista_unroll_backward``).  Holds a workspace (scratch of one call: calls
+    on different streams must not overlap) and a default checkpoint buffer that
+    ``forward`` / ``backward`` use unless given their own ``ckpt`` (from
+    ``new_checkpoints``); a backward must read the checkpoints of its own
+    forward.  ``tune``: launch shape as in ``solve``."""
 
     def __init__(self, plan, degree, iters, inv_l, ckpt_every=5, momentum=True, tune=0):
         import torch
@@ -506,8 +509,14 @@ class Unrolled:
         nws = int(lib.pfista_unroll_workspace_bytes(plan.handle, ctypes.byref(prm)))
         if nck == 0 or nws == 0:
             raise PfistaError(EINVAL, lib.pfista_last_error().decode() or "bad unroll parameters")
-        self.ckpt = torch.empty(nck, dtype=torch.uint8, device=plan.device)
+        self._nck = nck
+        self.ckpt = self.new_checkpoints()
         self.ws = torch.empty(nws, dtype=torch.uint8, device=plan.device)
+
+    def new_checkpoints(self):
+        """A checkpoint buffer for one forward pass (and its backward pass)."""
+        import torch
+        return torch.empty(self._nck, dtype=torch.uint8, device=self.plan.device)
 
     def _params(self, lam, coef):
         self._carr = (ctypes.c_double * len(coef))(*[float(v) for v in coef])
@@ -515,24 +524,28 @@ class Unrolled:
                              ctypes.cast(self._carr, ctypes.POINTER(ctypes.c_double)), self.iters,
                              self.ckpt_every, int(self.momentum), self.tune)
 
-    def forward(self, sens, mask, b, x, lam, coef, stream=None):
+    def forward(self, sens, mask, b, x, lam, coef, stream=None, ckpt=None):
         c, pl = _cplx(), self.plan
         if len(coef) != self.degree + 1:
             raise ValueError(f"expected {self.degree + 1} coefficients")
         prm = self._params(lam, coef)
+        ck = self.ckpt if ckpt is None else ckpt
         _check(load_library().pfista_unroll_forward(
             pl.handle, _ptr(sens, "sens", c, pl.n_coil), _ptr(mask, "mask", pl.mask_dtype(), pl.mask_numel),
-            _ptr(b, "b", c, pl.n_coil), ctypes.byref(prm), _ptr(x, "x", c, pl.n_img), _ptr(self.ckpt, "ckpt"),
-            _ptr(self.ws, "ws"), _stream(stream)))
+            _ptr(b, "b", c, pl.n_coil), ctypes.byref(prm), _ptr(x, "x", c, pl.n_img),
+            _ptr(ck, "ckpt", None, self._nck), _ptr(self.ws, "ws"), _stream(stream)))
 
-    def backward(self, sens, mask, x_bar, lam, coef, stream=None):
-        """(dL/dlambda, [dL/dc_0, ..., dL/dc_d]) for the cotangent x_bar."""
+    def backward(self, sens, mask, x_bar, lam, coef, stream=None, ckpt=None):
+        """(dL/dlambda, [dL/dc_0, ..., dL/dc_d]) for the cotangent x_bar, from
+        the checkpoints of the forward pass that wrote ``ckpt`` (default: the
+        object's own buffer)."""
         c, pl = _cplx(), self.plan
         prm = self._params(lam, coef)
         g = (ctypes.c_double * (self.degree + 2))()
+        ck = self.ckpt if ckpt is None else ckpt
         _check(load_library().pfista_unroll_backward(
             pl.handle, _ptr(sens, "sens", c, pl.n_coil), _ptr(mask, "mask", pl.mask_dtype(), pl.mask_numel),
-            ctypes.byref(prm), _ptr(x_bar, "x_bar", c, pl.n_img), _ptr(self.ckpt, "ckpt"), g,
+            ctypes.byref(prm), _ptr(x_bar, "x_bar", c, pl.n_img), _ptr(ck, "ckpt", None, self._nck), g,
             _ptr(self.ws, "ws"), _stream(stream)))
         return g[0], list(g)[1:]
 
@@ -546,15 +559,18 @@ def _unrolled_function():
             pl = unrolled.plan
             x = torch.empty((pl.slices, pl.n, pl.n), dtype=torch.complex64, device=sens.device)
             lv, cv = float(lam), [float(v) for v in coef.detach().cpu()]
-            unrolled.forward(sens, mask, b, x, lv, cv)
-            ctx.unrolled, ctx.args = unrolled, (sens, mask, lv, cv)
+            # every call keeps its own checkpoints, so that two forward passes
+            # before their backward passes each get their own gradient
+            ck = unrolled.new_checkpoints()
+            unrolled.forward(sens, mask, b, x, lv, cv, ckpt=ck)
+            ctx.unrolled, ctx.ckpt, ctx.args = unrolled, ck, (sens, mask, lv, cv)
             ctx.dtypes = (lam.dtype, coef.dtype, lam.device, coef.device)
             return x
 
         @staticmethod
         def backward(ctx, x_bar):
             sens, mask, lv, cv = ctx.args
-            gl, gc = ctx.unrolled.backward(sens, mask, x_bar.contiguous(), lv, cv)
+            gl, gc = ctx.unrolled.backward(sens, mask, x_bar.contiguous(), lv, cv, ckpt=ctx.ckpt)
             ld, cd, ldev, cdev = ctx.dtypes
             return (torch.tensor(gl, dtype=ld, device=ldev), torch.tensor(gc, dtype=cd, device=cdev),
                     None, None, None, None)
@@ -569,8 +585,8 @@ def unrolled_pfista(lam, coef, unrolled, sens, mask, b):
     """x_K of ``unrolled`` (an ``Unrolled``) as a differentiable function of the
     real tensors ``lam`` (0-d) and ``coef`` (d + 1), e.g.
     ``loss(unrolled_pfista(lam, coef, u, sens, mask, b)).backward()``.  The
-    backward pass runs ``pfista_unroll_backward`` (it must follow the forward
-    pass of the same call, whose checkpoints it reads)."""
+    backward pass runs ``pfista_unroll_backward`` on the checkpoints this call's
+    forward pass wrote (each call allocates its own)."""
     global _UNROLLED_FN
     if _UNROLLED_FN is None:
         _UNROLLED_FN = _unrolled_function()

@@ -207,9 +207,6 @@ template <int R, int DIR> __device__ __forceinline__ void dft(float2 *v) {
 // input pairs.  For a pair (a, w b) both results come from one product folded
 // into FMAs: s = a + w b (four FMAs) and a - w b = 2 a - s (two FMAs), six
 // operations where the separate product, sum and difference take eight.
-#ifndef PF_FFT_FMA_TW
-#define PF_FFT_FMA_TW 1
-#endif
 __device__ __forceinline__ void bfly_tw(float2 &a, float2 &b, float2 w) {
   float2 s;
   s.x = __builtin_fmaf(w.x, b.x, a.x);
@@ -366,13 +363,7 @@ __device__ __forceinline__ void stage_compute(float2 *v, int j0, const float2 *t
         w[r - 1] = tk[r - 1];
         if (DIR > 0) w[r - 1].y = -w[r - 1].y;
       }
-#if PF_FFT_FMA_TW
       dft_tw<R, DIR>(v + b * R, w);
-#else
-#pragma unroll
-      for (int r = 1; r < R; ++r) v[b * R + r] = cmul(v[b * R + r], w[r - 1]);
-      dft<R, DIR>(v + b * R);
-#endif
     } else {
       dft<R, DIR>(v + b * R);
     }

@@ -33,14 +33,7 @@ template <> struct Plans<64> { using F = Plan<64, 8, 8, 8>; using I = Plan<64, 8
 template <> struct Plans<128> { using F = Plan<128, 8, 16, 8>; using I = Plan<128, 8, 8, 16>; };
 template <> struct Plans<160> { using F = Plan<160, 16, 10, 16>; using I = Plan<160, 16, 16, 10>; };
 template <> struct Plans<192> { using F = Plan<192, 16, 12, 16>; using I = Plan<192, 16, 16, 12>; };
-#ifndef PF_PLAN256
-#define PF_PLAN256 0
-#endif
-#if PF_PLAN256 == 1
-template <> struct Plans<256> { using F = Plan<256, 32, 8, 8, 4>; using I = Plan<256, 32, 4, 8, 8>; };
-#else
 template <> struct Plans<256> { using F = Plan<256, 16, 16, 16>; using I = Plan<256, 16, 16, 16>; };
-#endif
 template <> struct Plans<320> { using F = Plan<320, 16, 20, 4, 4>; using I = Plan<320, 16, 4, 4, 20>; };
 template <> struct Plans<384> { using F = Plan<384, 16, 8, 8, 6>; using I = Plan<384, 16, 6, 8, 8>; };
 template <> struct Plans<512> { using F = Plan<512, 16, 8, 8, 8>; using I = Plan<512, 16, 8, 8, 8>; };
@@ -62,16 +55,7 @@ constexpr int kVariants = 2;
 // Plans of the one-pass phase-encode operator: fewer values per lane (more
 // lanes per transform) keep its four per-lane arrays within two waves per SIMD.
 template <int N> struct Plans1D { using F = typename Plans<N>::F; using I = typename Plans<N>::I; };
-#ifndef PF_PLAN1D384
-#define PF_PLAN1D384 2
-#endif
-#if PF_PLAN1D384 == 1
-template <> struct Plans1D<384> { using F = Plan<384, 16, 8, 8, 6>; using I = Plan<384, 16, 6, 8, 8>; };
-#elif PF_PLAN1D384 == 2
 template <> struct Plans1D<384> { using F = Plan<384, 32, 12, 8, 4>; using I = Plan<384, 32, 4, 8, 12>; };
-#else
-template <> struct Plans1D<384> { using F = Plan<384, 32, 12, 4, 4, 2>; using I = Plan<384, 32, 2, 4, 4, 12>; };
-#endif
 template <> struct Plans1D<320> { using F = Plan<320, 32, 10, 4, 8>; using I = Plan<320, 32, 8, 4, 10>; };
 template <> struct Plans1D<512> { using F = Plan<512, 32, 16, 4, 8>; using I = Plan<512, 32, 8, 4, 16>; };
 
@@ -103,11 +87,8 @@ template <int N, int V = 0> struct Geo : PairGeo<typename PlansV<N, V>::F, typen
 // the phase-encode kernel's blocks span 16 columns (128 B of every row of a
 // coil map) so that no cache line of the streamed coil maps is split between
 // blocks
-#ifndef PF_1D_BLOCK_WAVES
-#define PF_1D_BLOCK_WAVES 0
-#endif
 template <int N> struct Waves1D {
-  static constexpr int v = PF_1D_BLOCK_WAVES > 0 ? PF_1D_BLOCK_WAVES : 16 / (64 / Plans1D<N>::F::T);
+  static constexpr int v = 16 / (64 / Plans1D<N>::F::T);
 };
 template <int N> struct Geo1D : PairGeo<typename Plans1D<N>::F, typename Plans1D<N>::I, Waves1D<N>::v> {
   using F = typename Plans1D<N>::F;
@@ -872,20 +853,10 @@ __global__ __launch_bounds__(256) void k_nudft_adjoint(const float2 *__restrict_
 // Block = COLS columns of one slice, wave-private transform groups; all coils
 // are accumulated in registers; the next coil map is loaded after the
 // current one has been transformed and combined.
-#ifndef PF_1D_WAVES
-#define PF_1D_WAVES 2
-#endif
-// PF_1D_HOIST: let the compiler keep the per-lane index math of the transforms
-// in registers across the coil loop (a few spilled registers cost less than
-// recomputing it for every coil)
-#ifndef PF_1D_BUFLOAD
-#define PF_1D_BUFLOAD 1
-#endif
-#ifndef PF_1D_HOIST
-#define PF_1D_HOIST 1
-#endif
+// The per-lane index math of the transforms stays in registers across the coil
+// loop (the compiler hoists it; recomputing it for every coil costs more).
 template <int N>
-__global__ __launch_bounds__(Geo1D<N>::THREADS, PF_1D_WAVES) void k_normal_1d(const float2 *__restrict__ x,
+__global__ __launch_bounds__(Geo1D<N>::THREADS, 2) void k_normal_1d(const float2 *__restrict__ x,
                                                    const float2 *__restrict__ sens,
                                                    const uint8_t *__restrict__ mask,
                                                    float2 *__restrict__ y, const float2 *w, float alpha,
@@ -906,12 +877,10 @@ __global__ __launch_bounds__(Geo1D<N>::THREADS, PF_1D_WAVES) void k_normal_1d(co
   const uint8_t *mask_s = mask + (size_t)s * N;
   const float2 *xs = x + (size_t)s * N * N;
   const float2 *ss = sens + (size_t)s * C * N * N;
-#if PF_1D_BUFLOAD
   // buffer resource over this slice's coil maps (raw, byte-addressed; reads past
   // the end return zero)
   const __amdgpu_buffer_rsrc_t srsrc = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<float2 *>(ss), (short)0, C * N * N * (int)sizeof(float2), 0x00020000);
-#endif
   // positions yy = j + r * F::B_in (F input layout == I output layout)
   auto pos = [&](int i) { return (j0 + (i / F::R_in) * T + (i % F::R_in) * F::B_in) * N + kx; };
   auto okp = [&](int i) { return lay_in_ok<F>(j0 + (i / F::R_in) * T); };
@@ -937,13 +906,8 @@ __global__ __launch_bounds__(Geo1D<N>::THREADS, PF_1D_WAVES) void k_normal_1d(co
     float2 v[Gm::P];
 #pragma unroll
     for (int i = 0; i < PI; ++i) v[i] = cmul(sc[i], xv[i]);
-#if PF_1D_HOIST
     const int jl = j0;
     float2 *bl = s_buf + wv * Gm::CPW * Gm::LDSN + ci;
-#else
-    const int jl = opaque(j0);
-    float2 *bl = s_buf + wv * Gm::CPW * Gm::LDSN + opaque(ci);
-#endif
 
     fft_run<F, -1, Gm::CPW>(v, bl, jl, s_twF);
 #pragma unroll
@@ -953,7 +917,6 @@ __global__ __launch_bounds__(Geo1D<N>::THREADS, PF_1D_WAVES) void k_normal_1d(co
 #pragma unroll
     for (int i = 0; i < PI; ++i) acc[i] = cadd(acc[i], cmulc(v[i], sc[i]));
     if (c + 1 < C) {
-#if PF_1D_BUFLOAD
       // the next coil map through buffer loads: the per-lane byte offsets are the
       // same for every coil and the coil's offset is a scalar, so the loop does no
       // 64-bit address arithmetic per load
@@ -964,15 +927,6 @@ __global__ __launch_bounds__(Geo1D<N>::THREADS, PF_1D_WAVES) void k_normal_1d(co
         sc[i] = okp(i) ? __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(srsrc, o, soff, 0))
                        : make_float2(0.f, 0.f);
       }
-#else
-      const float2 *snp = ss + (size_t)(c + 1) * N * N;
-      const int kxl = PF_1D_HOIST ? kx : opaque(kx);
-#pragma unroll
-      for (int i = 0; i < PI; ++i) {
-        const int o = (jl + (i / F::R_in) * T + (i % F::R_in) * F::B_in) * N + kxl;
-        sc[i] = okp(i) ? snp[o] : make_float2(0.f, 0.f);
-      }
-#endif
     }
   }
   float2 *ys = y + (size_t)s * N * N;

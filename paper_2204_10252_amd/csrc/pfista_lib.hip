@@ -463,11 +463,16 @@ template <int N, int V = 0> struct Ops {
 const float2 *F2(const pfista_c32 *p) { return reinterpret_cast<const float2 *>(p); }
 float2 *F2(pfista_c32 *p) { return reinterpret_cast<float2 *>(p); }
 
+// y = alpha N x + beta w with the transform buffer t ([S][C][n][n], twice that
+// for a Toeplitz plan)
+void normal_op_t(const pfista_desc &d, const pfista_c32 *sens, const uint8_t *mask, const float2 *x, float2 *y,
+                 float alpha, const float2 *w, float beta, float2 *t, hipStream_t st, int *k_inc = nullptr) {
+  PF_DISPATCH(d.n, Ops<NN>::normal(shape_of(d), F2(sens), mask, x, y, alpha, w, beta, t, st, k_inc));
+}
+
 void normal_op(const pfista_desc &d, const pfista_c32 *sens, const uint8_t *mask, const float2 *x, float2 *y,
                float alpha, const float2 *w, float beta, void *ws, hipStream_t st, int *k_inc = nullptr) {
-  const Layout L = layout(d);
-  float2 *t = at<float2>(ws, L.t);
-  PF_DISPATCH(d.n, Ops<NN>::normal(shape_of(d), F2(sens), mask, x, y, alpha, w, beta, t, st, k_inc));
+  normal_op_t(d, sens, mask, x, y, alpha, w, beta, at<float2>(ws, layout(d).t), st, k_inc);
 }
 
 void reduce(const double *partials, int count, int width, double *out, int *k_dev, hipStream_t st) {
@@ -1026,6 +1031,22 @@ int pfista_solve(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *ma
     if (ie != hipSuccess) return fail(PFISTA_EHIP, "graph instantiate: %s", hipGetErrorString(ie));
   }
 
+  // device time of the loop (set-up excluded), on the solver's stream
+  struct LoopEvents {
+    hipEvent_t e[2] = {nullptr, nullptr};
+    ~LoopEvents() {
+      for (hipEvent_t v : e)
+        if (v) (void)hipEventDestroy(v);
+    }
+  } lev;
+  if (hipEventCreate(&lev.e[0]) != hipSuccess || hipEventCreate(&lev.e[1]) != hipSuccess) {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    return fail(PFISTA_EHIP, "pfista_solve: event create failed");
+  }
+  if (hipEventRecord(lev.e[0], stream) != hipSuccess) {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    return fail(PFISTA_EHIP, "pfista_solve: event record failed");
+  }
   int done = 0, nchecks = 0;
   int status = PFISTA_OK;
   while (done < prm->max_iter) {
@@ -1091,6 +1112,14 @@ int pfista_solve(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *ma
     if (prm->f_stop > 0 && prm->eval_objective && F <= prm->f_stop) break;
   }
   if (gexec) (void)hipGraphExecDestroy(gexec);
+  if (done > 0) {
+    float lms = 0.f;
+    hipError_t te = hipEventRecord(lev.e[1], stream);
+    if (te == hipSuccess) te = hipEventSynchronize(lev.e[1]);
+    if (te == hipSuccess) te = hipEventElapsedTime(&lms, lev.e[0], lev.e[1]);
+    if (te != hipSuccess) return fail(PFISTA_EHIP, "pfista_solve(loop timing): %s", hipGetErrorString(te));
+    r.loop_ms = lms;
+  }
   r.iters = done;
   r.status = status;
   r.normal_applies = (long long)done * (deg + 1);

@@ -178,6 +178,33 @@ def test_autograd_mse_to_phantom(w1):
     assert loss.item() == pytest.approx(float(np.mean(np.abs(scale * xo - inp["phantom"]) ** 2)), rel=1e-4)
 
 
+def test_autograd_two_forwards_before_their_backwards(w1):
+    # two calls on one Unrolled (different thresholds and data scale), then the
+    # backward passes in reverse order: each must get its own call's gradient
+    import torch
+    import paper_2204_10252_amd as pf
+    inp, sens, s128, b, bn, inv_l = w1
+    K, degree = 6, 2
+    u = gpu_unrolled(inp, degree, K, inv_l, ckpt_every=3)
+    cf = coefs(degree)
+    lam_a = smooth_lambda(inp, s128, bn, inv_l, cf, inp["levels"], K)
+    lam_b = smooth_lambda(inp, s128, bn, inv_l, cf, inp["levels"], K, lam0=3.0 * inp["lam"])
+    ts, tm, tb = to_dev(sens), to_dev(inp["mask"]), to_dev(b)
+    xbar_o = np.full(inp["phantom"].shape, 0.5 - 0.25j)
+    calls = []
+    for lam_v in (lam_a, lam_b):
+        lam = torch.tensor(lam_v, dtype=torch.float64, requires_grad=True)
+        coef = torch.tensor(cf, dtype=torch.float64, requires_grad=True)
+        x = pf.unrolled_pfista(lam, coef, u, ts, tm, tb)
+        # L = Re <x_bar, x>: its cotangent is x_bar
+        loss = torch.sum(torch.real(torch.conj(to_dev(c64(xbar_o))) * x))
+        calls.append((lam_v, lam, coef, loss))
+    for lam_v, lam, coef, loss in reversed(calls):
+        loss.backward()
+        ol, oc = orc.unrolled_vjp(s128, inp["mask"], bn, inv_l, lam_v, cf, inp["levels"], K, xbar_o)
+        close(np.concatenate([[lam.grad.item()], coef.grad.numpy()]), np.concatenate([[ol], oc]))
+
+
 def test_unrolled_rejects_bad_parameters(w1):
     import paper_2204_10252_amd as pf
     inp, sens, s128, b, bn, inv_l = w1
