@@ -146,3 +146,65 @@ def test_workload3_slab_solve_sampled_slices():
         bn = b[None].astype(np.complex128) / np.sqrt(bn2)
         xo, _, _ = orc.pfista(sens[None].astype(np.complex128), mask[None], bn, inv_l, lam, coef, 4, K)
         assert rel(x[s].cpu().numpy(), xo[0]) <= 1e-4, f"slice {s}"
+
+
+def _fullsize_inputs(wid, slices):
+    import torch
+    dev = torch.device("cuda", 0)
+    d0 = make_slice_inputs(wid, 0)
+    n, coils = d0["n"], d0["coils"]
+    ts = torch.empty((slices, coils, n, n), dtype=torch.complex64, device=dev)
+    tm = torch.empty((slices,) + d0["mask"].shape, dtype=torch.uint8, device=dev)
+    for s in range(slices):
+        d = d0 if s == 0 else make_slice_inputs(wid, s)
+        ts[s].copy_(torch.from_numpy(c64(d["sens"])))
+        tm[s].copy_(torch.from_numpy(d["mask"]))
+    return n, coils, ts, tm
+
+
+def _vdot(a, b):
+    """<a, b> = sum conj(a) b in FP64 on the host."""
+    return complex(np.vdot(a.cpu().numpy().astype(np.complex128).ravel(),
+                           b.cpu().numpy().astype(np.complex128).ravel()))
+
+
+@pytest.mark.parametrize("wid,slices,kind", [(2, 1, 0), (3, 32, 1)])
+def test_fullsize_operator_invariants(wid, slices, kind):
+    # the operator's own structure at full size, on random images: N Hermitian
+    # (<Nx, y> = <x, Ny>), 0 <= <x, Nx> <= ||x||^2 (sum_c |S_c|^2 = 1 and a
+    # unitary F put the spectrum in [0, 1]), and the forward/adjoint pair
+    # (<Ax, k> = <x, A^H k>); an indexing error anywhere in the passes breaks
+    # them even where a norm-wise comparison would average it away
+    import torch
+    import paper_2204_10252_amd as pf
+    n, coils, ts, tm = _fullsize_inputs(wid, slices)
+    plan = pf.Plan(n, coils, slices, haar_levels=4, mask_kind=kind)
+    g = torch.Generator(device="cuda").manual_seed(100 + wid)
+    shape = (slices, n, n)
+    x = torch.randn(shape, dtype=torch.complex64, device="cuda", generator=g)
+    y = torch.randn(shape, dtype=torch.complex64, device="cuda", generator=g)
+    nx, ny = torch.empty_like(x), torch.empty_like(y)
+    pf.normal_apply(plan, ts, tm, x, nx, 1.0)
+    pf.normal_apply(plan, ts, tm, y, ny, 1.0)
+    a, b = _vdot(nx, y), _vdot(x, ny)
+    scale = float(torch.linalg.vector_norm(nx)) * float(torch.linalg.vector_norm(y))
+    assert abs(a - b) <= 1e-6 * scale, (a, b)
+    q = _vdot(x, nx)
+    xx = float(torch.linalg.vector_norm(x)) ** 2
+    assert abs(q.imag) <= 1e-6 * xx
+    assert 0.0 < q.real <= xx * (1 + 1e-6)
+    # per slice too: each slice is its own block of the operator
+    for s in range(slices):
+        qs = _vdot(x[s], nx[s]).real
+        assert 0.0 < qs <= float(torch.linalg.vector_norm(x[s])) ** 2 * (1 + 1e-6)
+    k = torch.randn((slices, coils, n, n), dtype=torch.complex64, device="cuda", generator=g)
+    ax, ahk = torch.empty_like(k), torch.empty_like(x)
+    pf.forward(plan, ts, tm, x, ax)
+    pf.adjoint(plan, ts, tm, k, ahk, 1.0)
+    c, d = _vdot(ax, k), _vdot(x, ahk)
+    scale = float(torch.linalg.vector_norm(ax)) * float(torch.linalg.vector_norm(k))
+    assert abs(c - d) <= 1e-6 * scale, (c, d)
+    # and A^H A = adjoint(forward(.)): the apply equals the composition
+    ahax = torch.empty_like(x)
+    pf.adjoint(plan, ts, tm, ax, ahax, 1.0)
+    assert float(torch.linalg.vector_norm(ahax - nx)) <= 1e-5 * float(torch.linalg.vector_norm(nx))

@@ -239,10 +239,13 @@ def w2():
 @pytest.mark.parametrize("degree", [0, 1, 2, 3, 4, 5])
 def test_workload2_fp32_against_fp64_per_degree(w2, degree):
     # the FP32 path against the FP64 oracle at 256 x 256, 16 coils for plain FISTA
-    # (degree 0: p = 1) and every fitted degree, 30 iterations each
+    # (degree 0: p = 1) and every fitted degree, the workload's 200 iterations each
+    import os
+    import scipy.fft
     import torch
     import paper_2204_10252_amd as pf
     inp, sens, s128, b, bn, inv_l = w2
+    iters = 200
     plan = gpu_plan(inp)
     coef = [1.0] if degree == 0 else [float(c) for c in orc.l2_poly_coefficients(degree)]
     x = torch.empty((1, 256, 256), dtype=torch.complex64, device="cuda")
@@ -251,15 +254,39 @@ def test_workload2_fp32_against_fp64_per_degree(w2, degree):
     torch.cuda.synchronize()
     with torch.cuda.stream(s):
         # the benchmark's launch configuration: graph replay on a side stream
-        rep = pf.solve(*args, inp["lam"], coef=coef, max_iter=30, inv_l=inv_l, eval_objective=True,
+        rep = pf.solve(*args, inp["lam"], coef=coef, max_iter=iters, inv_l=inv_l, eval_objective=True,
                        graph_iters=10, stream=s)
     s.synchronize()
-    xo, _, hist = orc.pfista(s128, inp["mask"], bn, inv_l, inp["lam"], coef, inp["levels"], 30, history=True)
+    # the oracle's FFTs split over the host's cores (independent transforms: same values)
+    with scipy.fft.set_workers(min(16, os.cpu_count() or 1)):
+        xo, _, _ = orc.pfista(s128, inp["mask"], bn, inv_l, inp["lam"], coef, inp["levels"], iters)
+        fo = orc.objective(s128, inp["mask"], bn, inv_l, xo, inp["lam"], inp["levels"])
     err = rel(x.cpu().numpy(), xo)
-    print(f"W2 degree {degree}: final-iterate FP32 vs FP64 relative error {err:.2e}, objective "
-          f"{abs(rep['objective'] - hist[-1]) / hist[-1]:.2e}", flush=True)
+    print(f"W2 degree {degree}: {iters} iterations, final-iterate FP32 vs FP64 relative error {err:.2e}, "
+          f"objective {abs(rep['objective'] - fo) / fo:.2e}", flush=True)
     assert err <= 1e-4
-    assert rep["objective"] == pytest.approx(hist[-1], rel=1e-5)
+    assert rep["objective"] == pytest.approx(fo, rel=1e-5)
+
+
+def test_fixed_point_residual_of_a_converged_solve(c1):
+    # a converged GPU PFISTA run (d = 3) is a fixed point of its own map: the
+    # preconditioned fixed-point condition y = prox(y - P(N'y - A'^H b')), here
+    # evaluated in FP64 by the oracle on the GPU's final iterate
+    import torch
+    import paper_2204_10252_amd as pf
+    inp, sens, s128, b, bn, inv_l = c1
+    coef = [float(c) for c in orc.l2_poly_coefficients(3)]
+    plan = gpu_plan(inp)
+    x = torch.empty((inp["slices"], inp["n"], inp["n"]), dtype=torch.complex64, device="cuda")
+    pf.solve(plan, to_dev(sens), to_dev(inp["mask"]), to_dev(b), x, inp["lam"], coef=coef, max_iter=800,
+             inv_l=inv_l, graph_iters=10)
+    y = x.cpu().numpy().astype(np.complex128)
+    ahb = np.sqrt(inv_l) * orc.adjoint(s128, inp["mask"], bn)
+    g = orc.normal(s128, inp["mask"], y, inv_l) - ahb
+    ty = orc.prox_l1_haar(y - orc.poly_apply(s128, inp["mask"], inv_l, coef, g), inp["lam"], inp["levels"])
+    res = np.linalg.norm(ty - y) / np.linalg.norm(y)
+    print(f"fixed-point residual after 800 iterations: {res:.2e}", flush=True)
+    assert res <= 1e-4
 
 
 @pytest.mark.parametrize("degree,iters", [(0, 2000), (3, 600)])
