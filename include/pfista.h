@@ -108,6 +108,21 @@ int pfista_normal_apply(const pfista_plan *p, const pfista_c32 *sens, const uint
                         const pfista_c32 *x, pfista_c32 *y, float alpha, const pfista_c32 *w,
                         float beta, void *ws, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * operation as pfista_normal_apply, with its transform buffer in the library's
+ * own static device array of PFISTA_STATIC_SCRATCH_BYTES (32 MiB) instead of a
+ * caller workspace; it calls no allocating routine.  Each GPU holds one such
+ * array for the life of the process, shared by every call on that GPU: calls
+ * that overlap on one GPU (other streams, other threads) race.  The array's
+ * contents are left over from the last call; every element a call reads, it
+ * has written first.  EINVAL when the plan's transform buffer (S * C * n^2
+ * complex values, twice that for Toeplitz plans) exceeds the array. */
+#define PFISTA_STATIC_SCRATCH_BYTES (32u << 20)
+int pfista_normal_apply_noalloc(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *mask,
+                                const pfista_c32 *x, pfista_c32 *y, float alpha,
+                                const pfista_c32 *w, float beta, hipStream_t stream);
+
 /* Polynomial preconditioner (Section 2.7, nested evaluation):
  *   out = p(N') g,  N' = inv_l * A^H A,  p(z) = sum_{i=0..degree} coef[i] z^i,
  * evaluated as h = coef[d] g; h = coef[i] g + N' h for i = d-1 .. 0, i.e.

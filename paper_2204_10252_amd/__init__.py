@@ -16,7 +16,7 @@ import re
 
 __all__ = [
     "Plan", "PfistaError", "load_library", "library_path", "poly_coefficients",
-    "poly_coefficients_weighted", "poly_coefficients_chebyshev", "normal_apply", "poly_apply", "step", "forward", "adjoint", "data_term",
+    "poly_coefficients_weighted", "poly_coefficients_chebyshev", "normal_apply", "normal_apply_noalloc", "poly_apply", "step", "forward", "adjoint", "data_term",
     "power_iteration", "profile_normal", "solve", "MASK_2D", "MASK_1D", "TOEPLITZ", "header_functions",
     "toeplitz_kernel", "nudft_forward", "nudft_adjoint",
     "Batch", "batch_solve", "TUNE_CANDIDATES", "Unrolled", "unrolled_pfista", "image_scale",
@@ -96,6 +96,7 @@ _SIGS = {
     "pfista_plan_destroy": (None, [_VP]),
     "pfista_workspace_bytes": (ctypes.c_size_t, [_VP]),
     "pfista_normal_apply": (_I, [_VP, _VP, _VP, _VP, _VP, _F, _VP, _F, _VP, _VP]),
+    "pfista_normal_apply_noalloc": (_I, [_VP, _VP, _VP, _VP, _VP, _F, _VP, _F, _VP]),
     "pfista_poly_apply": (_I, [_VP, _VP, _VP, _D, ctypes.POINTER(_D), _I, _VP, _VP, _VP, _VP]),
     "pfista_step": (_I, [_VP, _VP, _VP, _VP, _VP, _VP, _F, _F, _VP, _VP, _VP]),
     "pfista_forward": (_I, [_VP, _VP, _VP, _VP, _VP, _VP, _VP]),
@@ -279,6 +280,18 @@ def normal_apply(plan, sens, mask, x, y, alpha=1.0, w=None, beta=0.0, stream=Non
         plan.handle, _ptr(sens, "sens", c, plan.n_coil), _ptr(mask, "mask", plan.mask_dtype(), plan.mask_numel),
         _ptr(x, "x", c, plan.n_img), _ptr(y, "y", c, plan.n_img), float(alpha),
         _ptr(w, "w", c, plan.n_img, allow_none=True), float(beta), _ptr(plan.ws, "ws"), _stream(stream)))
+    return y
+
+
+def normal_apply_noalloc(plan, sens, mask, x, y, alpha=1.0, w=None, beta=0.0, stream=None):
+    """``normal_apply`` without a workspace: the library's static per-device
+    scratch array holds the transform buffer (for callers that cannot allocate;
+    calls overlapping on one GPU race)."""
+    c = _cplx()
+    _check(load_library().pfista_normal_apply_noalloc(
+        plan.handle, _ptr(sens, "sens", c, plan.n_coil), _ptr(mask, "mask", plan.mask_dtype(), plan.mask_numel),
+        _ptr(x, "x", c, plan.n_img), _ptr(y, "y", c, plan.n_img), float(alpha),
+        _ptr(w, "w", c, plan.n_img, allow_none=True), float(beta), _stream(stream)))
     return y
 
 

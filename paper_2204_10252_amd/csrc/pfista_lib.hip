@@ -69,6 +69,13 @@ bool supported_toeplitz_n(int n) { return n <= 256 && supported_n(2 * n); }
 std::mutex g_tw_mu;
 std::vector<int> g_tw_done;
 
+// Static transform buffer of pfista_normal_apply_noalloc, one per device.  Host
+// code never uses the array's name as an address: each device's copy is looked
+// up once (hipGetSymbolAddress, with that device current) when the first plan
+// on the device is created, and that pointer is what kernels receive.
+__device__ __align__(256) unsigned char scratch[PFISTA_STATIC_SCRATCH_BYTES];
+std::vector<void *> g_scratch_ptr;
+
 // exp(-2 pi i r k / (Ns R)) for every stage of plan PL, in its TwLayout order
 template <class PL> void fill_plan_tw(std::vector<float2> &h, int base) {
   for (int st = 0; st < PL::NST; ++st) {
@@ -110,8 +117,19 @@ int ensure_twiddles() {
   fill_n<512>(h);
   PF_HIP(hipMemcpyToSymbol(HIP_SYMBOL(pf::g_tw), h.data(), h.size() * sizeof(float2), 0,
                            hipMemcpyHostToDevice));
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+  void *sp = nullptr;
+  PF_HIP(hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)));
+  if (!sp) return fail(PFISTA_EHIP, "no device address for the static scratch array");
+  g_scratch_ptr[dev] = sp;
   g_tw_done[dev] = 1;
   return PFISTA_OK;
+}
+
+// this device's static scratch array (set up with its first plan), or null
+void *device_scratch(int dev) {
+  std::lock_guard<std::mutex> lk(g_tw_mu);
+  return dev >= 0 && dev < (int)g_scratch_ptr.size() ? g_scratch_ptr[dev] : nullptr;
 }
 
 // ------------------------------------------------------------------ workspace
@@ -707,6 +725,31 @@ int pfista_normal_apply(const pfista_plan *p, const pfista_c32 *sens, const uint
   if (w && w != y && overlaps(w, nb, y, nb)) return fail(PFISTA_EINVAL, "w partially overlaps y");
   normal_op(p->d, sens, mask, F2(x), F2(y), alpha, w ? F2(w) : nullptr, beta, ws, stream);
   return launch_status("pfista_normal_apply");
+}
+
+int pfista_normal_apply_noalloc(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *mask,
+                                const pfista_c32 *x, pfista_c32 *y, float alpha, const pfista_c32 *w, float beta,
+                                hipStream_t stream) {
+  PF_TRY(check_plan(p));
+  if (p->d.slices == 0) return PFISTA_OK;
+  PF_TRY(check_ptr(sens, "sens"));
+  PF_TRY(check_ptr(mask, "mask", 1));
+  PF_TRY(check_ptr(x, "x"));
+  PF_TRY(check_ptr(y, "y"));
+  if (w) PF_TRY(check_ptr(w, "w"));
+  const Layout L = layout(p->d);
+  if (L.n_img == 0) return PFISTA_OK;
+  const size_t need = L.img[0] - L.t;   // the transform buffer's section of a workspace
+  if (need > PFISTA_STATIC_SCRATCH_BYTES)
+    return fail(PFISTA_EINVAL, "transform buffer of %zu bytes exceeds the static scratch of %u bytes", need,
+                (unsigned)PFISTA_STATIC_SCRATCH_BYTES);
+  const size_t nb = L.n_img * sizeof(float2);
+  if (overlaps(x, nb, y, nb)) return fail(PFISTA_EINVAL, "y overlaps x");
+  if (w && w != y && overlaps(w, nb, y, nb)) return fail(PFISTA_EINVAL, "w partially overlaps y");
+  float2 *t = static_cast<float2 *>(device_scratch(p->device));
+  if (!t) return fail(PFISTA_EHIP, "static scratch of device %d is not set up", p->device);
+  normal_op_t(p->d, sens, mask, F2(x), F2(y), alpha, w ? F2(w) : nullptr, beta, t, stream);
+  return launch_status("pfista_normal_apply_noalloc");
 }
 
 int pfista_poly_apply(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *mask, double inv_l,
