@@ -95,7 +95,9 @@ void pfista_plan_destroy(pfista_plan *p);
 
 /* Workspace size in bytes needed by every call on this plan (including
  * pfista_solve at any degree <= 8): one complex64 per (slice, coil, pixel),
- * five images, and small FP64 scratch. */
+ * five images, and small FP64 scratch; phase-encode plans add one more
+ * complex64 per (slice, coil, pixel), where pfista_solve keeps the packed coil
+ * maps its loop reads (see pfista_pack_coil_maps). */
 size_t pfista_workspace_bytes(const pfista_plan *p);
 
 /* Normal operator (the paper's A^H A, Section 2.7 counts these):
@@ -131,6 +133,30 @@ int pfista_normal_apply_noalloc(const pfista_plan *p, const pfista_c32 *sens, co
 int pfista_poly_apply(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *mask,
                       double inv_l, const double *coef, int degree, const pfista_c32 *g,
                       pfista_c32 *out, void *ws, hipStream_t stream);
+
+/* Coil maps of a phase-encode plan in the layout its one-pass operator
+ * (Section 2.7's A^H A with F^H M F acting along the phase-encode axis only)
+ * reads fastest: `packed` receives the same S * C * N * N complex values,
+ * reordered so that every load of the operator's coil loop is one contiguous
+ * 1 KB run per wavefront.  The order is internal to this library version: the
+ * only valid uses of `packed` are the *_packed calls below on a plan of the
+ * same desc.  Cost: one read and one write of the coil maps.  `packed` (device,
+ * 16-byte aligned, caller-owned) must not overlap `sens`.  UNSUPPORTED for
+ * 2-D and Toeplitz plans. */
+int pfista_pack_coil_maps(const pfista_plan *p, const pfista_c32 *sens, pfista_c32 *packed,
+                          hipStream_t stream);
+
+/* pfista_normal_apply and pfista_poly_apply of a phase-encode plan with the
+ * coil maps given packed (from pfista_pack_coil_maps): the same arithmetic in
+ * the same order, so bitwise the same results.  UNSUPPORTED for other plans;
+ * `packed` must be 16-byte aligned.  pfista_solve packs the maps into its
+ * workspace by itself. */
+int pfista_normal_apply_packed(const pfista_plan *p, const pfista_c32 *packed, const uint8_t *mask,
+                               const pfista_c32 *x, pfista_c32 *y, float alpha, const pfista_c32 *w,
+                               float beta, void *ws, hipStream_t stream);
+int pfista_poly_apply_packed(const pfista_plan *p, const pfista_c32 *packed, const uint8_t *mask,
+                             double inv_l, const double *coef, int degree, const pfista_c32 *g,
+                             pfista_c32 *out, void *ws, hipStream_t stream);
 
 /* Fused proximal and momentum step of Algorithm 4 (prox of Section 2.1):
  *   x_new = Psi^H soft(Psi (z - pg), lambda)

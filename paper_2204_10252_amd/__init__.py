@@ -16,7 +16,8 @@ import re
 
 __all__ = [
     "Plan", "PfistaError", "load_library", "library_path", "poly_coefficients",
-    "poly_coefficients_weighted", "poly_coefficients_chebyshev", "normal_apply", "normal_apply_noalloc", "poly_apply", "step", "forward", "adjoint", "data_term",
+    "poly_coefficients_weighted", "poly_coefficients_chebyshev", "normal_apply", "normal_apply_noalloc", "poly_apply",
+    "pack_coil_maps", "normal_apply_packed", "poly_apply_packed", "step", "forward", "adjoint", "data_term",
     "power_iteration", "profile_normal", "solve", "MASK_2D", "MASK_1D", "TOEPLITZ", "header_functions",
     "toeplitz_kernel", "nudft_forward", "nudft_adjoint",
     "Batch", "batch_solve", "TUNE_CANDIDATES", "Unrolled", "unrolled_pfista", "image_scale",
@@ -98,6 +99,9 @@ _SIGS = {
     "pfista_normal_apply": (_I, [_VP, _VP, _VP, _VP, _VP, _F, _VP, _F, _VP, _VP]),
     "pfista_normal_apply_noalloc": (_I, [_VP, _VP, _VP, _VP, _VP, _F, _VP, _F, _VP]),
     "pfista_poly_apply": (_I, [_VP, _VP, _VP, _D, ctypes.POINTER(_D), _I, _VP, _VP, _VP, _VP]),
+    "pfista_pack_coil_maps": (_I, [_VP, _VP, _VP, _VP]),
+    "pfista_normal_apply_packed": (_I, [_VP, _VP, _VP, _VP, _VP, _F, _VP, _F, _VP, _VP]),
+    "pfista_poly_apply_packed": (_I, [_VP, _VP, _VP, _D, ctypes.POINTER(_D), _I, _VP, _VP, _VP, _VP]),
     "pfista_step": (_I, [_VP, _VP, _VP, _VP, _VP, _VP, _F, _F, _VP, _VP, _VP]),
     "pfista_forward": (_I, [_VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "pfista_adjoint": (_I, [_VP, _VP, _VP, _VP, _VP, _F, _VP, _VP]),
@@ -300,6 +304,39 @@ def poly_apply(plan, sens, mask, inv_l, coef, g, out, stream=None):
     arr = (ctypes.c_double * len(coef))(*[float(v) for v in coef])
     _check(load_library().pfista_poly_apply(
         plan.handle, _ptr(sens, "sens", c, plan.n_coil), _ptr(mask, "mask", plan.mask_dtype(), plan.mask_numel),
+        float(inv_l), arr, len(coef) - 1, _ptr(g, "g", c, plan.n_img), _ptr(out, "out", c, plan.n_img),
+        _ptr(plan.ws, "ws"), _stream(stream)))
+    return out
+
+
+def pack_coil_maps(plan, sens, packed=None, stream=None):
+    """Coil maps of a phase-encode plan in the layout its operator streams fastest
+    (same size as ``sens``; valid only for the ``*_packed`` calls on this plan's shape)."""
+    import torch
+    c = _cplx()
+    if packed is None:
+        packed = torch.empty(plan.n_coil, dtype=c, device=sens.device)
+    _check(load_library().pfista_pack_coil_maps(
+        plan.handle, _ptr(sens, "sens", c, plan.n_coil), _ptr(packed, "packed", c, plan.n_coil), _stream(stream)))
+    return packed
+
+
+def normal_apply_packed(plan, packed, mask, x, y, alpha=1.0, w=None, beta=0.0, stream=None):
+    """``normal_apply`` of a phase-encode plan on packed coil maps (bitwise the same result)."""
+    c = _cplx()
+    _check(load_library().pfista_normal_apply_packed(
+        plan.handle, _ptr(packed, "packed", c, plan.n_coil), _ptr(mask, "mask", plan.mask_dtype(), plan.mask_numel),
+        _ptr(x, "x", c, plan.n_img), _ptr(y, "y", c, plan.n_img), float(alpha),
+        _ptr(w, "w", c, plan.n_img, allow_none=True), float(beta), _ptr(plan.ws, "ws"), _stream(stream)))
+    return y
+
+
+def poly_apply_packed(plan, packed, mask, inv_l, coef, g, out, stream=None):
+    """``poly_apply`` of a phase-encode plan on packed coil maps (bitwise the same result)."""
+    c = _cplx()
+    arr = (ctypes.c_double * len(coef))(*[float(v) for v in coef])
+    _check(load_library().pfista_poly_apply_packed(
+        plan.handle, _ptr(packed, "packed", c, plan.n_coil), _ptr(mask, "mask", plan.mask_dtype(), plan.mask_numel),
         float(inv_l), arr, len(coef) - 1, _ptr(g, "g", c, plan.n_img), _ptr(out, "out", c, plan.n_img),
         _ptr(plan.ws, "ws"), _stream(stream)))
     return out

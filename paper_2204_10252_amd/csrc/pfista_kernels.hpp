@@ -848,14 +848,66 @@ __global__ __launch_bounds__(256) void k_nudft_adjoint(const float2 *__restrict_
 }
 
 // ---------------------------------------------------------------------------
+// Packed coil maps of the phase-encode operator.  In the natural layout one load
+// instruction of a k_normal_1d wave touches T rows and only CPW * 8 bytes of each
+// (the wave holds CPW columns: 32 rows x 16 bytes at N = 384), which keeps the
+// texture address unit busy; the packed layout stores, per slice, the values in
+// the order the kernel's lanes consume them: [column block][coil][wave][pair p]
+// [lane][h], where lane l's element i = 2p + h is its natural value at row pos_i
+// (zero where the plan's layout has no row).  A wave then reads one coil's pair
+// p as 1 KB of contiguous bytes (64 lanes x 16 bytes).  Same size as the natural
+// layout.
+template <int N> struct Pack1D {
+  using Gm = Geo1D<N>;
+  using F = typename Gm::F;
+  static constexpr int PI = Gm::P_IN;
+  static constexpr int W = Gm::THREADS / 64;
+  static_assert(PI % 2 == 0, "packed pairs need an even value count per lane");
+  static constexpr int PAIRS = PI / 2;
+  static constexpr unsigned PAIR_BYTES = 64u * 16u;                 // one pair of a wave
+  static constexpr unsigned COIL_BYTES = (unsigned)W * PAIRS * PAIR_BYTES;   // one coil of a block
+};
+
+// natural -> packed, one thread per packed element; grid (ceil(C N^2 / 256), S)
+template <int N>
+__global__ __launch_bounds__(256) void k_pack_1d(const float2 *__restrict__ sens, float2 *__restrict__ out, int C) {
+  using P = Pack1D<N>;
+  using Gm = typename P::Gm;
+  using F = typename P::F;
+  const size_t per_slice = (size_t)C * N * N;
+  const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= per_slice) return;
+  const int s = blockIdx.y;
+  size_t q = e;
+  const int h = (int)(q % 2);
+  q /= 2;
+  const int ln = (int)(q % 64);
+  q /= 64;
+  const int pr = (int)(q % P::PAIRS);
+  q /= P::PAIRS;
+  const int wv = (int)(q % P::W);
+  q /= P::W;
+  const int c = (int)(q % C);
+  const int bx = (int)(q / C);
+  const int i = 2 * pr + h;
+  const int j0 = ln / Gm::CPW;
+  const int kx = bx * Gm::COLS + wv * Gm::CPW + ln % Gm::CPW;
+  const int yy = j0 + (i / F::R_in) * F::T + (i % F::R_in) * F::B_in;
+  const float2 *src = sens + (size_t)s * per_slice + (size_t)c * N * N;
+  out[(size_t)s * per_slice + e] =
+      lay_in_ok<F>(j0 + (i / F::R_in) * F::T) ? src[(size_t)yy * N + kx] : make_float2(0.f, 0.f);
+}
+
+// ---------------------------------------------------------------------------
 // One-pass normal operator for a phase-encode mask (sampled rows ky, all kx):
 // F^H M F = (F_y^H M_y F_y) (x) I, so each column only needs a y transform pair.
 // Block = COLS columns of one slice, wave-private transform groups; all coils
 // are accumulated in registers; the next coil map is loaded after the
-// current one has been transformed and combined.
+// current one has been transformed and combined.  PACKED: `sens` is in the
+// packed layout above (same arithmetic, so bitwise the same result).
 // The per-lane index math of the transforms stays in registers across the coil
 // loop (the compiler hoists it; recomputing it for every coil costs more).
-template <int N>
+template <int N, bool PACKED>
 __global__ __launch_bounds__(Geo1D<N>::THREADS, 2) void k_normal_1d(const float2 *__restrict__ x,
                                                    const float2 *__restrict__ sens,
                                                    const uint8_t *__restrict__ mask,
@@ -893,12 +945,28 @@ __global__ __launch_bounds__(Geo1D<N>::THREADS, 2) void k_normal_1d(const float2
       if (lay_out_ok<F>(j) && mask_s[j + r * F::B_out] != 0) mbits |= 1u << (b * F::R_out + r);
   }
   float2 xv[PI], acc[PI], sc[PI];
+  // packed: this lane's first pair within coil 0 of its block; a coil adds a
+  // scalar offset, a pair a constant one
+  using Pk = Pack1D<N>;
+  const unsigned lane_off =
+      PACKED ? ((((unsigned)blockIdx.x * C * Pk::W + wv) * Pk::PAIRS) * 64u + ln) * 16u : 0u;
+  auto load_packed = [&](int c) {
+#pragma unroll
+    for (int p = 0; p < Pk::PAIRS; ++p) {
+      const float4 f = __builtin_bit_cast(
+          float4, __builtin_amdgcn_raw_buffer_load_b128(srsrc, lane_off + p * Pk::PAIR_BYTES,
+                                                        (int)(c * Pk::COIL_BYTES), 0));
+      sc[2 * p] = make_float2(f.x, f.y);
+      sc[2 * p + 1] = make_float2(f.z, f.w);
+    }
+  };
 #pragma unroll
   for (int i = 0; i < PI; ++i) {
     xv[i] = okp(i) ? xs[pos(i)] : make_float2(0.f, 0.f);
-    sc[i] = okp(i) ? ss[pos(i)] : make_float2(0.f, 0.f);
+    if constexpr (!PACKED) sc[i] = okp(i) ? ss[pos(i)] : make_float2(0.f, 0.f);
     acc[i] = make_float2(0.f, 0.f);
   }
+  if constexpr (PACKED) load_packed(0);
   load_tw(s_twF, TwBase<N>::v + TwBlock<N>::f1, TwLayout<F>::size());
   load_tw(s_twI, TwBase<N>::v + TwBlock<N>::i1, TwLayout<I>::size());
   __syncthreads();
@@ -920,12 +988,16 @@ __global__ __launch_bounds__(Geo1D<N>::THREADS, 2) void k_normal_1d(const float2
       // the next coil map through buffer loads: the per-lane byte offsets are the
       // same for every coil and the coil's offset is a scalar, so the loop does no
       // 64-bit address arithmetic per load
-      const int soff = (c + 1) * N * N * (int)sizeof(float2);
+      if constexpr (PACKED) {
+        load_packed(c + 1);
+      } else {
+        const int soff = (c + 1) * N * N * (int)sizeof(float2);
 #pragma unroll
-      for (int i = 0; i < PI; ++i) {
-        const unsigned o = (unsigned)((j0 + (i / F::R_in) * T + (i % F::R_in) * F::B_in) * N + kx) * 8u;
-        sc[i] = okp(i) ? __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(srsrc, o, soff, 0))
-                       : make_float2(0.f, 0.f);
+        for (int i = 0; i < PI; ++i) {
+          const unsigned o = (unsigned)((j0 + (i / F::R_in) * T + (i % F::R_in) * F::B_in) * N + kx) * 8u;
+          sc[i] = okp(i) ? __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(srsrc, o, soff, 0))
+                         : make_float2(0.f, 0.f);
+        }
       }
     }
   }

@@ -181,6 +181,14 @@ Layout layout(const pfista_desc &d) {
 
 template <class T> T *at(void *ws, size_t off) { return reinterpret_cast<T *>(static_cast<char *>(ws) + off); }
 
+// pfista_solve's workspace: the layout above, then (phase-encode plans) the
+// packed coil maps its loop reads
+size_t solve_packed_off(const pfista_desc &d) { return align_up(layout(d).total); }
+size_t solve_ws_bytes(const pfista_desc &d) {
+  const Layout L = layout(d);
+  return d.mask_kind == PFISTA_MASK_1D ? solve_packed_off(d) + align_up(L.n_coil * sizeof(float2)) : L.total;
+}
+
 // ------------------------------------------------------------------ validation
 // a plan (or batch) belongs to the device that was current when it was created
 int check_device(int dev) {
@@ -236,10 +244,11 @@ struct Shape {
   int cmin;         // smallest coil count of a slice (sizes the coil-combine passes)
   int rpw_mult;     // rows per coil-combine block, as a multiple of the default
   int fused;        // fuse the row passes between the applies of a chain
+  int packed;       // phase-encode mask: `sens` holds the packed coil maps
 };
 
 Shape shape_of(const pfista_desc &d) {
-  return Shape{d.slices, d.coils, d.slices * d.coils, d.haar_levels, d.mask_kind, nullptr, nullptr, d.coils, 1, 1};
+  return Shape{d.slices, d.coils, d.slices * d.coils, d.haar_levels, d.mask_kind, nullptr, nullptr, d.coils, 1, 1, 0};
 }
 
 // Toeplitz normal operator with transforms of length M = 2N (image side N);
@@ -367,7 +376,10 @@ template <int N, int V = 0> struct Ops {
       if (d.mask_kind == PFISTA_MASK_1D) {
         using G1 = pf::Geo1D<N>;
         const dim3 grid(N / G1::COLS, d.slices);
-        pf::k_normal_1d<N><<<grid, G1::THREADS, 0, st>>>(x, sens, mask, y, w, alpha / (float)N, beta, d.coils, k_inc);
+        if (d.packed)
+          pf::k_normal_1d<N, true><<<grid, G1::THREADS, 0, st>>>(x, sens, mask, y, w, alpha / (float)N, beta, d.coils, k_inc);
+        else
+          pf::k_normal_1d<N, false><<<grid, G1::THREADS, 0, st>>>(x, sens, mask, y, w, alpha / (float)N, beta, d.coils, k_inc);
         return;
       }
     }
@@ -426,6 +438,13 @@ template <int N, int V = 0> struct Ops {
 
   // k_dev: a valid device int; use_k != 0 takes beta = k / (k + 3) from it;
   // lam_s: per-slice thresholds (device) or nullptr for `lam`
+  // natural -> packed coil maps of a phase-encode plan
+  static void pack_1d(const Shape &d, const float2 *sens, float2 *out, hipStream_t st) {
+    const size_t per = (size_t)d.coils * N * N;
+    const dim3 grid((unsigned)((per + 255) / 256), d.slices);
+    pf::k_pack_1d<N><<<grid, 256, 0, st>>>(sens, out, d.coils);
+  }
+
   static void step(const Shape &d, const float2 *z, const float2 *pg, const float2 *xo, float2 *xn,
                    float2 *zn, float pg_scale, float lam, float beta, const int *k_dev, int use_k,
                    double *partials, hipStream_t st, const float *lam_s = nullptr) {
@@ -483,9 +502,13 @@ float2 *F2(pfista_c32 *p) { return reinterpret_cast<float2 *>(p); }
 
 // y = alpha N x + beta w with the transform buffer t ([S][C][n][n], twice that
 // for a Toeplitz plan)
+// packed != 0: `sens` holds the packed coil maps of a phase-encode plan
 void normal_op_t(const pfista_desc &d, const pfista_c32 *sens, const uint8_t *mask, const float2 *x, float2 *y,
-                 float alpha, const float2 *w, float beta, float2 *t, hipStream_t st, int *k_inc = nullptr) {
-  PF_DISPATCH(d.n, Ops<NN>::normal(shape_of(d), F2(sens), mask, x, y, alpha, w, beta, t, st, k_inc));
+                 float alpha, const float2 *w, float beta, float2 *t, hipStream_t st, int *k_inc = nullptr,
+                 int packed = 0) {
+  Shape sh = shape_of(d);
+  sh.packed = packed;
+  PF_DISPATCH(d.n, Ops<NN>::normal(sh, F2(sens), mask, x, y, alpha, w, beta, t, st, k_inc));
 }
 
 void normal_op(const pfista_desc &d, const pfista_c32 *sens, const uint8_t *mask, const float2 *x, float2 *y,
@@ -545,22 +568,23 @@ int plan_candidate_ok(const pfista_desc &d, int cand) { return d.mask_kind == PF
 // a plan's chain of applies in the launch shape of candidate `cand`
 void chain_shaped(const pfista_desc &d, int cand, const pfista_c32 *sens, const uint8_t *mask, const float2 *x0,
                   int m, const float *alpha, const float *beta, const float2 *const *w, float2 *const *y, float2 *t,
-                  hipStream_t st, int *k_inc) {
+                  hipStream_t st, int *k_inc, int packed = 0) {
   cand = plan_candidate_ok(d, cand);
   Shape sh = shape_of(d);
   sh.rpw_mult = 1 << (cand / 4);
   sh.fused = (cand / 2) % 2 ? 0 : 1;
+  sh.packed = packed;
   PF_DISPATCH_V(d.n, cand % 2, Ops<NN, VV>::chain(sh, F2(sens), mask, x0, m, alpha, beta, w, y, t, st, k_inc));
 }
 
 void grad_poly_op(const pfista_desc &d, const pfista_c32 *sens, const uint8_t *mask, double inv_l,
                   const std::vector<double> &c, const float2 *pre_x, const float2 *pre_w, float2 *g,
-                  float2 *out, void *ws, hipStream_t st, int *k_inc, int cand = 0) {
+                  float2 *out, void *ws, hipStream_t st, int *k_inc, int cand = 0, int packed = 0) {
   const int deg = (int)c.size() - 1;
   const Layout L = layout(d);
   float2 *t = at<float2>(ws, L.t);
   const Chain ch = make_chain(inv_l, c, pre_x, pre_w, g, out);
-  if (ch.m > 0) chain_shaped(d, cand, sens, mask, ch.x0, ch.m, ch.alpha, ch.beta, ch.w, ch.y, t, st, k_inc);
+  if (ch.m > 0) chain_shaped(d, cand, sens, mask, ch.x0, ch.m, ch.alpha, ch.beta, ch.w, ch.y, t, st, k_inc, packed);
   if (deg == 0 && !pre_x) pf::k_scale<<<blocks_for(L.n_img), 256, 0, st>>>(g, out, L.n_img, (float)c[0]);
 }
 
@@ -570,8 +594,8 @@ int tune_plan(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *mask,
               double &best_us);
 
 void poly_op(const pfista_desc &d, const pfista_c32 *sens, const uint8_t *mask, double inv_l,
-             const std::vector<double> &c, const float2 *g, float2 *out, void *ws, hipStream_t st) {
-  grad_poly_op(d, sens, mask, inv_l, c, nullptr, nullptr, const_cast<float2 *>(g), out, ws, st, nullptr);
+             const std::vector<double> &c, const float2 *g, float2 *out, void *ws, hipStream_t st, int packed = 0) {
+  grad_poly_op(d, sens, mask, inv_l, c, nullptr, nullptr, const_cast<float2 *>(g), out, ws, st, nullptr, 0, packed);
 }
 
 int l2_coefficients(int d, std::vector<double> &c) {
@@ -646,6 +670,15 @@ int chebyshev_coefficients(int d, double mu, std::vector<double> &c) {
   return PFISTA_OK;
 }
 
+// entry checks of the calls that take packed coil maps
+int check_packed_plan(const pfista_plan *p, const pfista_c32 *packed, const uint8_t *mask, const void *ws) {
+  PF_TRY(check_ops(p, packed, mask, ws));
+  if (p->d.mask_kind != PFISTA_MASK_1D)
+    return fail(PFISTA_UNSUPPORTED, "packed coil maps exist for phase-encode plans only");
+  if (p->d.slices > 0) PF_TRY(check_ptr(packed, "packed", 16));
+  return PFISTA_OK;
+}
+
 }  // namespace
 
 // ============================================================================ C-ABI
@@ -683,7 +716,7 @@ void pfista_plan_destroy(pfista_plan *p) { delete p; }
 
 size_t pfista_workspace_bytes(const pfista_plan *p) {
   if (!p) return 0;
-  return layout(p->d).total;
+  return solve_ws_bytes(p->d);
 }
 
 int pfista_poly_coefficients(int degree, double *coef) {
@@ -768,6 +801,57 @@ int pfista_poly_apply(const pfista_plan *p, const pfista_c32 *sens, const uint8_
   std::vector<double> c(coef, coef + degree + 1);
   poly_op(p->d, sens, mask, inv_l, c, F2(g), F2(out), ws, stream);
   return launch_status("pfista_poly_apply");
+}
+
+int pfista_pack_coil_maps(const pfista_plan *p, const pfista_c32 *sens, pfista_c32 *packed, hipStream_t stream) {
+  PF_TRY(check_plan(p));
+  if (p->d.mask_kind != PFISTA_MASK_1D)
+    return fail(PFISTA_UNSUPPORTED, "packed coil maps exist for phase-encode plans only");
+  if (p->d.slices == 0) return PFISTA_OK;
+  PF_TRY(check_ptr(sens, "sens"));
+  PF_TRY(check_ptr(packed, "packed", 16));
+  const Layout L = layout(p->d);
+  if (L.n_coil == 0) return PFISTA_OK;
+  const size_t nb = L.n_coil * sizeof(float2);
+  if (overlaps(sens, nb, packed, nb)) return fail(PFISTA_EINVAL, "packed overlaps sens");
+  PF_DISPATCH(p->d.n, Ops<NN>::pack_1d(shape_of(p->d), F2(sens), F2(packed), stream));
+  return launch_status("pfista_pack_coil_maps");
+}
+
+int pfista_normal_apply_packed(const pfista_plan *p, const pfista_c32 *packed, const uint8_t *mask,
+                               const pfista_c32 *x, pfista_c32 *y, float alpha, const pfista_c32 *w, float beta,
+                               void *ws, hipStream_t stream) {
+  PF_TRY(check_packed_plan(p, packed, mask, ws));
+  if (p->d.slices == 0) return PFISTA_OK;
+  PF_TRY(check_ptr(x, "x"));
+  PF_TRY(check_ptr(y, "y"));
+  if (w) PF_TRY(check_ptr(w, "w"));
+  const Layout L = layout(p->d);
+  if (L.n_img == 0) return PFISTA_OK;
+  const size_t nb = L.n_img * sizeof(float2);
+  if (overlaps(x, nb, y, nb)) return fail(PFISTA_EINVAL, "y overlaps x");
+  if (w && w != y && overlaps(w, nb, y, nb)) return fail(PFISTA_EINVAL, "w partially overlaps y");
+  normal_op_t(p->d, packed, mask, F2(x), F2(y), alpha, w ? F2(w) : nullptr, beta, at<float2>(ws, L.t), stream,
+              nullptr, 1);
+  return launch_status("pfista_normal_apply_packed");
+}
+
+int pfista_poly_apply_packed(const pfista_plan *p, const pfista_c32 *packed, const uint8_t *mask, double inv_l,
+                             const double *coef, int degree, const pfista_c32 *g, pfista_c32 *out, void *ws,
+                             hipStream_t stream) {
+  PF_TRY(check_packed_plan(p, packed, mask, ws));
+  if (p->d.slices == 0) return PFISTA_OK;
+  PF_TRY(check_ptr(g, "g"));
+  PF_TRY(check_ptr(out, "out"));
+  if (!coef) return fail(PFISTA_EINVAL, "coef is NULL");
+  if (degree < 0 || degree > kMaxDegree) return fail(PFISTA_UNSUPPORTED, "degree %d outside 0..%d", degree, kMaxDegree);
+  const Layout L = layout(p->d);
+  if (L.n_img == 0) return PFISTA_OK;
+  const size_t nb = L.n_img * sizeof(float2);
+  if (overlaps(g, nb, out, nb)) return fail(PFISTA_EINVAL, "out overlaps g");
+  std::vector<double> c(coef, coef + degree + 1);
+  poly_op(p->d, packed, mask, inv_l, c, F2(g), F2(out), ws, stream, 1);
+  return launch_status("pfista_poly_apply_packed");
 }
 
 int pfista_step(const pfista_plan *p, const pfista_c32 *z, const pfista_c32 *pg, const pfista_c32 *x_old,
@@ -1036,6 +1120,15 @@ int pfista_solve(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *ma
   set_counter(ds, k0 - 1, stream);   // the first gradient apply advances it to k0
   PF_TRY(launch_status("pfista_solve(setup)"));
 
+  // phase-encode plans: the loop reads the coil maps in the packed layout
+  const int packed = d.mask_kind == PFISTA_MASK_1D ? 1 : 0;
+  const pfista_c32 *loop_sens = sens;
+  if (packed) {
+    pfista_c32 *spk = at<pfista_c32>(ws, solve_packed_off(d));
+    PF_DISPATCH(d.n, Ops<NN>::pack_1d(shape_of(d), F2(sens), F2(spk), stream));
+    PF_TRY(launch_status("pfista_solve(pack)"));
+    loop_sens = spk;
+  }
   const int deg = (int)c.size() - 1;
   const float lam = (float)prm->lambda;
   const int nstep = (d.n / 16) * (d.n / 16) * d.slices;
@@ -1052,7 +1145,7 @@ int pfista_solve(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *ma
   auto body = [&]() {
     // g = N' z - A'^H b' then pg = p(N') g as one chain of d + 1 applies (its
     // first kernel advances the iteration counter k); then the fused step
-    grad_poly_op(d, sens, mask, inv_l, c, zb, ahb, g, pgb, ws, stream, &ds->k, cand);
+    grad_poly_op(d, loop_sens, mask, inv_l, c, zb, ahb, g, pgb, ws, stream, &ds->k, cand, packed);
     const float2 *pg = deg == 0 ? g : pgb;
     const float pg_scale = deg == 0 ? (float)c[0] : 1.f;
     // momentum off (Algorithms 1 and 3): beta = 0, so z_(k+1) = x_(k+1)

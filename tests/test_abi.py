@@ -61,6 +61,12 @@ def test_null_plan_is_rejected(lib):
     rc = lib.pfista_normal_apply(None, None, None, None, None, 1.0, None, 0.0, None, None)
     assert rc == -1
     assert b"plan" in lib.pfista_last_error()
+    # the packed-coil-map calls check the plan first too
+    assert lib.pfista_pack_coil_maps(None, None, None, None) == -1
+    assert b"plan" in lib.pfista_last_error()
+    assert lib.pfista_normal_apply_packed(None, None, None, None, None, 1.0, None, 0.0, None, None) == -1
+    coef = (ctypes.c_double * 2)(1.0, 0.5)
+    assert lib.pfista_poly_apply_packed(None, None, None, 1.0, coef, 1, None, None, None, None) == -1
 
 
 @pytest.mark.parametrize("d", range(0, 7))

@@ -4,8 +4,9 @@
   oracle (it finishes in well under a second at this size).
 * slab of 32 slices 384 x 384, 32 coils, phase-encode mask: the GPU applies the
   operator to all 32 slices at once; the oracle recomputes three sampled
-  slices (slices are independent blocks of A); likewise 8 PFISTA iterations
-  (d = 4) of the whole slab against the oracle on two slices.
+  slices (slices are independent blocks of A), and the apply on packed coil
+  maps equals it bit for bit; likewise 8 PFISTA iterations (d = 4) of the whole
+  slab against the oracle on two slices.
 * the plan's limit of 65535 coil images.
 Bar: relative l2 error <= 1e-5 per checked slice for applies and steps, 1e-4 for
 iterates.
@@ -59,6 +60,12 @@ def test_workload3_slab_sampled_slices():
     for s, (sens, mask, xs) in keep.items():
         ref = orc.normal(sens[None].astype(np.complex128), mask[None], xs[None].astype(np.complex128))
         assert rel(got[s], ref[0]) <= 1e-5, f"slice {s}"
+    # the packed coil maps the benchmark streams: bitwise the same apply
+    packed = pf.pack_coil_maps(plan, ts)
+    del ts
+    ty2 = torch.empty_like(tx)
+    pf.normal_apply_packed(plan, packed, tm, tx, ty2, 1.0)
+    assert torch.equal(torch.view_as_real(ty).view(torch.int32), torch.view_as_real(ty2).view(torch.int32))
 
 
 @pytest.mark.parametrize("slices,coils,kind", [(4369, 15, "2d"), (65535, 1, "2d"), (65535, 1, "1d")])

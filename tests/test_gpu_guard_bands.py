@@ -68,6 +68,10 @@ def test_entry_points_write_only_their_outputs(n, coils, slices, levels, kind):
 
     pf.normal_apply(plan, ts, tm, tx, out(img), 0.5, w=tw, beta=0.25)
     pf.poly_apply(plan, ts, tm, 0.9, [4.0, -10.0 / 3.0], tx, out(img))
+    if kind == pf.MASK_1D:
+        packed = pf.pack_coil_maps(plan, ts, out((plan.n_coil,)))
+        pf.normal_apply_packed(plan, packed, tm, tx, out(img), 0.5, w=tw, beta=0.25)
+        pf.poly_apply_packed(plan, packed, tm, 0.9, [4.0, -10.0 / 3.0], tx, out(img))
     xn, zn, red = out(img), out(img), out((3,), torch.float64)
     pf.step(plan, tx, tw, tw, xn, zn, 0.05, 0.25, red)
     if kind != pf.TOEPLITZ:

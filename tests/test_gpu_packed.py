@@ -1,0 +1,127 @@
+"""Packed coil maps of the phase-encode operator (through the C-ABI).
+
+The packed layout only reorders the coil maps so that the one-pass operator's
+loads are contiguous; the arithmetic and its order are those of the natural
+layout, so the bar is bitwise equality with ``normal_apply`` / ``poly_apply``
+(which are parity-tested against the FP64 oracle), plus one direct oracle check.
+Sizes: every supported image side, coil and slice counts that are not
+multiples of anything in the kernel, and the 32-slice 384^2 x 32-coil slab.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as orc
+from tests.gpu_util import HORNER_PARTIAL_MAX, oracle_normal, random_case, rel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+CASES = [(64, 1, 2), (128, 3, 1), (160, 5, 2), (192, 2, 3), (256, 7, 1), (320, 3, 2), (384, 5, 1), (512, 2, 1)]
+
+
+def _same_bits(a, b):
+    import torch
+    return torch.equal(torch.view_as_real(a).view(torch.int32), torch.view_as_real(b).view(torch.int32))
+
+
+@pytest.mark.parametrize("n,coils,slices", CASES)
+def test_packed_apply_is_bitwise_the_natural_apply(n, coils, slices):
+    import torch
+    import paper_2204_10252_amd as pf
+    sens, mask, x, w = random_case(n, coils, slices, "1d", seed=11 * n + coils)
+    plan = pf.Plan(n, coils, slices, haar_levels=4, mask_kind=pf.MASK_1D)
+    ts, tm, tx, tw = to_dev(sens), to_dev(mask), to_dev(x), to_dev(w)
+    packed = pf.pack_coil_maps(plan, ts)
+    # a permutation of the same values (no row is dropped or repeated at these shapes)
+    a = torch.sort(torch.view_as_real(ts).reshape(-1)).values
+    b = torch.sort(torch.view_as_real(packed).reshape(-1)).values
+    assert torch.equal(a, b)
+    y0, y1 = torch.empty_like(tx), torch.empty_like(tx)
+    for alpha, wt, beta in ((0.7, tw, -0.3), (1.0, None, 0.0)):
+        pf.normal_apply(plan, ts, tm, tx, y0, alpha, wt, beta)
+        pf.normal_apply_packed(plan, packed, tm, tx, y1, alpha, wt, beta)
+        assert _same_bits(y0, y1)
+    # w aliasing y
+    y0.copy_(tw)
+    y1.copy_(tw)
+    pf.normal_apply(plan, ts, tm, tx, y0, 0.7, y0, -0.3)
+    pf.normal_apply_packed(plan, packed, tm, tx, y1, 0.7, y1, -0.3)
+    assert _same_bits(y0, y1)
+    # and against the oracle directly
+    pf.normal_apply_packed(plan, packed, tm, tx, y1, 1.0)
+    ref = oracle_normal(sens, mask, x)
+    for s in range(slices):
+        assert rel(y1.cpu().numpy()[s], ref[s]) <= 1e-5
+
+
+@pytest.mark.parametrize("degree", [0, 3, 4])
+def test_packed_poly_apply_is_bitwise_the_natural_poly_apply(degree):
+    import torch
+    import paper_2204_10252_amd as pf
+    n, coils = 384, 6
+    sens, mask, g, _ = random_case(n, coils, 2, "1d", seed=degree + 5)
+    plan = pf.Plan(n, coils, 2, haar_levels=4, mask_kind=pf.MASK_1D)
+    ts, tm, tg = to_dev(sens), to_dev(mask), to_dev(g)
+    packed = pf.pack_coil_maps(plan, ts)
+    coef = pf.poly_coefficients(degree)
+    o0, o1 = torch.empty_like(tg), torch.empty_like(tg)
+    pf.poly_apply(plan, ts, tm, 1.0 / 1.01, coef, tg, o0)
+    pf.poly_apply_packed(plan, packed, tm, 1.0 / 1.01, coef, tg, o1)
+    assert _same_bits(o0, o1)
+    ref = orc.poly_apply(sens.astype(np.complex128), mask, 1.0 / 1.01, coef, g.astype(np.complex128))
+    assert rel(o1.cpu().numpy(), ref) <= 1e-5 * HORNER_PARTIAL_MAX[degree]
+
+
+def test_packed_calls_reject_other_plans_and_misuse():
+    import torch
+    import paper_2204_10252_amd as pf
+    n, coils = 64, 2
+    sens, mask, x, _ = random_case(n, coils, 1, "2d", seed=1)
+    plan2 = pf.Plan(n, coils, 1, haar_levels=3, mask_kind=pf.MASK_2D)
+    ts, tm, tx = to_dev(sens), to_dev(mask), to_dev(x)
+    with pytest.raises(pf.PfistaError) as e:
+        pf.pack_coil_maps(plan2, ts)
+    assert e.value.code == pf.UNSUPPORTED
+    with pytest.raises(pf.PfistaError) as e:
+        pf.normal_apply_packed(plan2, ts, tm, tx, torch.empty_like(tx))
+    assert e.value.code == pf.UNSUPPORTED
+    plan1 = pf.Plan(n, coils, 1, haar_levels=3, mask_kind=pf.MASK_1D)
+    # packed output overlapping the maps
+    with pytest.raises(pf.PfistaError) as e:
+        pf.pack_coil_maps(plan1, ts, ts)
+    assert e.value.code == pf.EINVAL
+    # a packed buffer that is not 16-byte aligned
+    raw = torch.empty(plan1.n_coil + 1, dtype=torch.complex64, device=tx.device)
+    off = raw[1:]
+    with pytest.raises(pf.PfistaError) as e:
+        pf.pack_coil_maps(plan1, ts, off)
+    assert e.value.code == pf.EINVAL
+    m1 = to_dev(np.ones((1, n), dtype=np.uint8))
+    with pytest.raises(pf.PfistaError) as e:
+        pf.normal_apply_packed(plan1, off, m1, tx, torch.empty_like(tx))
+    assert e.value.code == pf.EINVAL
+    # zero slices: nothing to do
+    plan0 = pf.Plan(n, coils, 0, haar_levels=3, mask_kind=pf.MASK_1D)
+    assert pf.load_library().pfista_pack_coil_maps(plan0.handle, None, None, None) == 0
+
+
+def test_solve_on_a_phase_encode_plan_uses_the_workspace_beyond_the_operator_layout():
+    """The solver packs the coil maps into the extra workspace of a phase-encode
+    plan: its result equals a solve whose workspace tail was filled with garbage
+    first (the packed maps are rewritten each call), bit for bit."""
+    import torch
+    import paper_2204_10252_amd as pf
+    n, coils = 192, 4
+    sens, mask, x, _ = random_case(n, coils, 2, "1d", seed=9)
+    plan = pf.Plan(n, coils, 2, haar_levels=3, mask_kind=pf.MASK_1D)
+    ts, tm = to_dev(sens), to_dev(mask)
+    b = torch.empty((2, coils, n, n), dtype=torch.complex64, device=ts.device)
+    pf.forward(plan, ts, tm, to_dev(x), b)
+    outs = []
+    for fill in (0, 0x5A):
+        plan.ws.fill_(fill)
+        xo = torch.empty((2, n, n), dtype=torch.complex64, device=ts.device)
+        pf.solve(plan, ts, tm, b, xo, lam=1e-3, degree=2, max_iter=12, inv_l=0.9, check_every=12)
+        outs.append(xo)
+    assert _same_bits(outs[0], outs[1])
+    assert torch.isfinite(torch.view_as_real(outs[0])).all()
