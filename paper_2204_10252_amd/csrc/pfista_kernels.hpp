@@ -944,20 +944,23 @@ __global__ __launch_bounds__(Geo1D<N>::THREADS, 2) void k_normal_1d(const float2
     for (int r = 0; r < F::R_out; ++r)
       if (lay_out_ok<F>(j) && mask_s[j + r * F::B_out] != 0) mbits |= 1u << (b * F::R_out + r);
   }
-  float2 xv[PI], acc[PI], sc[PI];
+  // packed: the next coil's maps go to `sn` between the forward and the inverse
+  // transform (contiguous loads leave the texture unit free enough for that
+  // overlap; natural-layout loads wait until the combine is done)
+  float2 xv[PI], acc[PI], sc[PI], sn[PACKED ? PI : 1];
   // packed: this lane's first pair within coil 0 of its block; a coil adds a
   // scalar offset, a pair a constant one
   using Pk = Pack1D<N>;
   const unsigned lane_off =
       PACKED ? ((((unsigned)blockIdx.x * C * Pk::W + wv) * Pk::PAIRS) * 64u + ln) * 16u : 0u;
-  auto load_packed = [&](int c) {
+  auto load_packed = [&](float2 *dst, int c) {
 #pragma unroll
     for (int p = 0; p < Pk::PAIRS; ++p) {
       const float4 f = __builtin_bit_cast(
           float4, __builtin_amdgcn_raw_buffer_load_b128(srsrc, lane_off + p * Pk::PAIR_BYTES,
                                                         (int)(c * Pk::COIL_BYTES), 0));
-      sc[2 * p] = make_float2(f.x, f.y);
-      sc[2 * p + 1] = make_float2(f.z, f.w);
+      dst[2 * p] = make_float2(f.x, f.y);
+      dst[2 * p + 1] = make_float2(f.z, f.w);
     }
   };
 #pragma unroll
@@ -966,7 +969,7 @@ __global__ __launch_bounds__(Geo1D<N>::THREADS, 2) void k_normal_1d(const float2
     if constexpr (!PACKED) sc[i] = okp(i) ? ss[pos(i)] : make_float2(0.f, 0.f);
     acc[i] = make_float2(0.f, 0.f);
   }
-  if constexpr (PACKED) load_packed(0);
+  if constexpr (PACKED) load_packed(sc, 0);
   load_tw(s_twF, TwBase<N>::v + TwBlock<N>::f1, TwLayout<F>::size());
   load_tw(s_twI, TwBase<N>::v + TwBlock<N>::i1, TwLayout<I>::size());
   __syncthreads();
@@ -981,23 +984,25 @@ __global__ __launch_bounds__(Geo1D<N>::THREADS, 2) void k_normal_1d(const float2
 #pragma unroll
     for (int i = 0; i < Gm::P_OUT; ++i)
       if (!((mbits >> i) & 1u)) v[i] = make_float2(0.f, 0.f);
+    if constexpr (PACKED) {
+      if (c + 1 < C) load_packed(sn, c + 1);
+    }
     fft_run<I, +1, Gm::CPW>(v, bl, jl, s_twI);
 #pragma unroll
     for (int i = 0; i < PI; ++i) acc[i] = cadd(acc[i], cmulc(v[i], sc[i]));
-    if (c + 1 < C) {
+    if constexpr (PACKED) {
+#pragma unroll
+      for (int i = 0; i < PI; ++i) sc[i] = sn[i];
+    } else if (c + 1 < C) {
       // the next coil map through buffer loads: the per-lane byte offsets are the
       // same for every coil and the coil's offset is a scalar, so the loop does no
       // 64-bit address arithmetic per load
-      if constexpr (PACKED) {
-        load_packed(c + 1);
-      } else {
-        const int soff = (c + 1) * N * N * (int)sizeof(float2);
+      const int soff = (c + 1) * N * N * (int)sizeof(float2);
 #pragma unroll
-        for (int i = 0; i < PI; ++i) {
-          const unsigned o = (unsigned)((j0 + (i / F::R_in) * T + (i % F::R_in) * F::B_in) * N + kx) * 8u;
-          sc[i] = okp(i) ? __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(srsrc, o, soff, 0))
-                         : make_float2(0.f, 0.f);
-        }
+      for (int i = 0; i < PI; ++i) {
+        const unsigned o = (unsigned)((j0 + (i / F::R_in) * T + (i % F::R_in) * F::B_in) * N + kx) * 8u;
+        sc[i] = okp(i) ? __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(srsrc, o, soff, 0))
+                       : make_float2(0.f, 0.f);
       }
     }
   }
