@@ -387,7 +387,7 @@ def batch_benchmark(torch, pf, dev, stream, graph_iters=10, k_short=10, k_long=6
     out = {"workload": "64 uneven slices, N in {128,160,192,256,320}, C in {8,12,16,32}, "
                        "2-D variable-density masks R ~ U[3,8], per-slice lambda, 4-level Haar",
            "degree": 3, "algorithmic_bytes_per_apply_sweep": sweep_bytes, "configs": {}}
-    for name, kw in (("tuned_16MB_groups_4_branches", dict(chunk_mb=16, tune=-1, streams=4)),
+    for name, kw in (("tuned_32MB_groups_4_branches", dict(chunk_mb=32, tune=-1, streams=4)),
                      ("tuned_2_branches", dict(tune=-1, streams=2)),
                      ("tuned_1_branch", dict(tune=-1, streams=1)),
                      ("default_1_branch", dict(tune=0, streams=1))):
