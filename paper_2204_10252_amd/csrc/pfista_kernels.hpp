@@ -868,34 +868,33 @@ template <int N> struct Pack1D {
   static constexpr unsigned COIL_BYTES = (unsigned)W * PAIRS * PAIR_BYTES;   // one coil of a block
 };
 
-// natural -> packed, one thread per packed element; grid (ceil(C N^2 / 256), S)
+// natural -> packed.  Block = one (column block, coil, slice): it reads the
+// block's COLS columns of every row (whole 128-byte row segments), places each
+// value at its packed position in LDS, and writes the block's packed run of
+// COLS * N values contiguously.  Every plan of this operator has one input
+// register block (NB_in = 1) with T == B_in, so row y is element i = y / T of
+// lane row j0 = y % T and no packed slot is padding.
 template <int N>
 __global__ __launch_bounds__(256) void k_pack_1d(const float2 *__restrict__ sens, float2 *__restrict__ out, int C) {
   using P = Pack1D<N>;
   using Gm = typename P::Gm;
   using F = typename P::F;
-  const size_t per_slice = (size_t)C * N * N;
-  const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= per_slice) return;
-  const int s = blockIdx.y;
-  size_t q = e;
-  const int h = (int)(q % 2);
-  q /= 2;
-  const int ln = (int)(q % 64);
-  q /= 64;
-  const int pr = (int)(q % P::PAIRS);
-  q /= P::PAIRS;
-  const int wv = (int)(q % P::W);
-  q /= P::W;
-  const int c = (int)(q % C);
-  const int bx = (int)(q / C);
-  const int i = 2 * pr + h;
-  const int j0 = ln / Gm::CPW;
-  const int kx = bx * Gm::COLS + wv * Gm::CPW + ln % Gm::CPW;
-  const int yy = j0 + (i / F::R_in) * F::T + (i % F::R_in) * F::B_in;
-  const float2 *src = sens + (size_t)s * per_slice + (size_t)c * N * N;
-  out[(size_t)s * per_slice + e] =
-      lay_in_ok<F>(j0 + (i / F::R_in) * F::T) ? src[(size_t)yy * N + kx] : make_float2(0.f, 0.f);
+  static_assert(F::NB_in == 1 && F::T == F::B_in, "packed order assumes one input block of T rows");
+  constexpr int COLS = Gm::COLS, RUN = COLS * N;
+  static_assert(RUN * (int)sizeof(float2) <= 65536, "one block's run must fit the workgroup's LDS");
+  __shared__ float2 s_run[RUN];
+  const int bx = blockIdx.x, c = blockIdx.y, s = blockIdx.z;
+  const float2 *src = sens + ((size_t)s * C + c) * N * N + (size_t)bx * COLS;
+  for (int e = threadIdx.x; e < RUN; e += 256) {
+    const int y = e / COLS, cl = e % COLS;
+    const int wv = cl / Gm::CPW, ci = cl % Gm::CPW;
+    const int j0 = y % F::T, i = y / F::T;
+    const int ln = j0 * Gm::CPW + ci;
+    s_run[((wv * P::PAIRS + i / 2) * 64 + ln) * 2 + (i % 2)] = src[(size_t)y * N + cl];
+  }
+  __syncthreads();
+  float2 *dst = out + (size_t)s * C * N * N + ((size_t)bx * C + c) * RUN;
+  for (int e = threadIdx.x; e < RUN; e += 256) dst[e] = s_run[e];
 }
 
 // ---------------------------------------------------------------------------

@@ -440,8 +440,7 @@ template <int N, int V = 0> struct Ops {
   // lam_s: per-slice thresholds (device) or nullptr for `lam`
   // natural -> packed coil maps of a phase-encode plan
   static void pack_1d(const Shape &d, const float2 *sens, float2 *out, hipStream_t st) {
-    const size_t per = (size_t)d.coils * N * N;
-    const dim3 grid((unsigned)((per + 255) / 256), d.slices);
+    const dim3 grid(N / pf::Geo1D<N>::COLS, d.coils, d.slices);
     pf::k_pack_1d<N><<<grid, 256, 0, st>>>(sens, out, d.coils);
   }
 
