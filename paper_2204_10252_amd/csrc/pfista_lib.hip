@@ -182,7 +182,8 @@ Layout layout(const pfista_desc &d) {
 template <class T> T *at(void *ws, size_t off) { return reinterpret_cast<T *>(static_cast<char *>(ws) + off); }
 
 // pfista_solve's workspace: the layout above, then (phase-encode plans) the
-// packed coil maps its loop reads
+// packed coil maps its loop reads when it runs at least kPackMinApplies applies
+constexpr long long kPackMinApplies = 12;
 size_t solve_packed_off(const pfista_desc &d) { return align_up(layout(d).total); }
 size_t solve_ws_bytes(const pfista_desc &d) {
   const Layout L = layout(d);
@@ -1119,8 +1120,11 @@ int pfista_solve(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *ma
   set_counter(ds, k0 - 1, stream);   // the first gradient apply advances it to k0
   PF_TRY(launch_status("pfista_solve(setup)"));
 
-  // phase-encode plans: the loop reads the coil maps in the packed layout
-  const int packed = d.mask_kind == PFISTA_MASK_1D ? 1 : 0;
+  // phase-encode plans: the loop reads the coil maps in the packed layout when
+  // the solve is long enough to repay the packing (one read and one write of the
+  // maps, about what 11 applies save); the results are the same bit for bit
+  const long long solve_applies = (long long)prm->max_iter * (long long)c.size();
+  const int packed = d.mask_kind == PFISTA_MASK_1D && solve_applies >= kPackMinApplies ? 1 : 0;
   const pfista_c32 *loop_sens = sens;
   if (packed) {
     pfista_c32 *spk = at<pfista_c32>(ws, solve_packed_off(d));

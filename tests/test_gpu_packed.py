@@ -105,23 +105,26 @@ def test_packed_calls_reject_other_plans_and_misuse():
     assert pf.load_library().pfista_pack_coil_maps(plan0.handle, None, None, None) == 0
 
 
-def test_solve_on_a_phase_encode_plan_uses_the_workspace_beyond_the_operator_layout():
-    """The solver packs the coil maps into the extra workspace of a phase-encode
-    plan: its result equals a solve whose workspace tail was filled with garbage
-    first (the packed maps are rewritten each call), bit for bit."""
+def test_packed_solve_equals_resumed_solves_on_natural_maps():
+    """A phase-encode solve of at least 12 applies packs its coil maps into the
+    workspace; single-iteration calls (3 applies each) read them in place.
+    Resumed from (x, z, k) they must reproduce the packed solve bit for bit
+    (resuming is bitwise exact), whatever the workspace held before."""
     import torch
     import paper_2204_10252_amd as pf
-    n, coils = 192, 4
-    sens, mask, x, _ = random_case(n, coils, 2, "1d", seed=9)
-    plan = pf.Plan(n, coils, 2, haar_levels=3, mask_kind=pf.MASK_1D)
+    n, coils, slices, iters = 192, 4, 2, 6
+    sens, mask, x, _ = random_case(n, coils, slices, "1d", seed=9)
+    plan = pf.Plan(n, coils, slices, haar_levels=3, mask_kind=pf.MASK_1D)
     ts, tm = to_dev(sens), to_dev(mask)
-    b = torch.empty((2, coils, n, n), dtype=torch.complex64, device=ts.device)
+    b = torch.empty((slices, coils, n, n), dtype=torch.complex64, device=ts.device)
     pf.forward(plan, ts, tm, to_dev(x), b)
-    outs = []
-    for fill in (0, 0x5A):
-        plan.ws.fill_(fill)
-        xo = torch.empty((2, n, n), dtype=torch.complex64, device=ts.device)
-        pf.solve(plan, ts, tm, b, xo, lam=1e-3, degree=2, max_iter=12, inv_l=0.9, check_every=12)
-        outs.append(xo)
-    assert _same_bits(outs[0], outs[1])
-    assert torch.isfinite(torch.view_as_real(outs[0])).all()
+    shp = (slices, n, n)
+    plan.ws.fill_(0x5A)
+    x1, z1 = (torch.empty(shp, dtype=torch.complex64, device=ts.device) for _ in range(2))
+    pf.solve(plan, ts, tm, b, x1, lam=1e-3, degree=2, max_iter=iters, inv_l=0.9, z=z1, check_every=iters)
+    plan.ws.fill_(0x33)
+    x2, z2 = (torch.empty(shp, dtype=torch.complex64, device=ts.device) for _ in range(2))
+    for k in range(iters):
+        pf.solve(plan, ts, tm, b, x2, lam=1e-3, degree=2, max_iter=1, inv_l=0.9, z=z2, k0=k, check_every=1)
+    assert _same_bits(x1, x2) and _same_bits(z1, z2)
+    assert torch.isfinite(torch.view_as_real(x1)).all()
