@@ -122,6 +122,28 @@ __device__ __forceinline__ void load_tw(float2 *dst, int off, int count) {
   for (int i = threadIdx.x; i < count; i += blockDim.x) dst[i] = g_tw[off + i];
 }
 
+// A twiddle table fetched into registers first and stored to LDS later: global
+// loads issued in between stay in flight across the store (a load_tw right after
+// them would wait for all of them).
+template <int COUNT, int TH> struct TwRegs {
+  static constexpr int K = (COUNT + TH - 1) / TH;
+  float2 r[K];
+  __device__ __forceinline__ void fetch(int off) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = (int)threadIdx.x + k * TH;
+      if (i < COUNT) r[k] = g_tw[off + i];
+    }
+  }
+  __device__ __forceinline__ void store(float2 *dst) const {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = (int)threadIdx.x + k * TH;
+      if (i < COUNT) dst[i] = r[k];
+    }
+  }
+};
+
 __device__ __forceinline__ double wave_sum_d(double v) {
   for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
   return v;
@@ -192,6 +214,9 @@ __global__ __launch_bounds__(256) void k_row_fwd(const float2 *__restrict__ x,
   }
   const float2 *xr = x + ((size_t)s * N + yy) * N;
   const float2 *sr = sens + ((size_t)cim * N + yy) * N;
+  // twiddles first: their LDS store and the barrier need not wait for the rows
+  TwRegs<TwLayout<F>::size(), Gm::THREADS> twf;
+  twf.fetch(Gm::TWF);
   float2 v[Gm::P];
 #pragma unroll
   for (int b = 0; b < F::NB_in; ++b) {
@@ -203,7 +228,7 @@ __global__ __launch_bounds__(256) void k_row_fwd(const float2 *__restrict__ x,
       v[b * F::R_in + r] = ok ? cmul(sr[i], xr[i]) : make_float2(0.f, 0.f);
     }
   }
-  load_tw(s_tw, Gm::TWF, TwLayout<F>::size());
+  twf.store(s_tw);
   __syncthreads();
   fft_run<F, -1>(v, s_buf[g], j0, s_tw);
   float2 *tr = t + ((size_t)cim * N + yy) * N;
@@ -254,15 +279,16 @@ __global__ __launch_bounds__(256, 2) void k_col(float2 *__restrict__ t, const fl
 
   // sampling flags at the k-space positions this lane holds (F's output layout)
   unsigned mbits = 0;
-#pragma unroll
-  for (int b = 0; b < F::NB_out; ++b) {
-    const int j = j0 + b * T;
-#pragma unroll
-    for (int r = 0; r < F::R_out; ++r)
-      if (lay_out_ok<F>(j) && sampled<MASK1D>(mask_s, j + r * F::B_out, kx, N)) mbits |= 1u << (b * F::R_out + r);
-  }
 
   if constexpr (MODE == COL_ADJ_IN) {
+    // the flags decide which k-space values are read at all
+#pragma unroll
+    for (int b = 0; b < F::NB_out; ++b) {
+      const int j = j0 + b * T;
+#pragma unroll
+      for (int r = 0; r < F::R_out; ++r)
+        if (lay_out_ok<F>(j) && sampled<MASK1D>(mask_s, j + r * F::B_out, kx, N)) mbits |= 1u << (b * F::R_out + r);
+    }
     const float2 *kc = kin + (size_t)sc * N * N;
 #pragma unroll
     for (int b = 0; b < I::NB_in; ++b) {
@@ -276,6 +302,12 @@ __global__ __launch_bounds__(256, 2) void k_col(float2 *__restrict__ t, const fl
     load_tw(s_twI, Gm::TWI, TwLayout<I>::size());
     __syncthreads();
   } else {
+    // issue order: twiddles, the column, the mask bytes; the flags are needed
+    // only after the forward transform, which runs while they arrive
+    TwRegs<TwLayout<F>::size(), Gm::THREADS> twf;
+    TwRegs<MODE == COL_NORMAL ? TwLayout<I>::size() : 1, Gm::THREADS> twi;
+    twf.fetch(Gm::TWF);
+    if constexpr (MODE == COL_NORMAL) twi.fetch(Gm::TWI);
 #pragma unroll
     for (int b = 0; b < F::NB_in; ++b) {
       const int j = j0 + b * T;
@@ -286,10 +318,24 @@ __global__ __launch_bounds__(256, 2) void k_col(float2 *__restrict__ t, const fl
         v[b * F::R_in + r] = ok ? tc[(size_t)yy * N + kx] : make_float2(0.f, 0.f);
       }
     }
-    load_tw(s_twF, Gm::TWF, TwLayout<F>::size());
-    if constexpr (MODE == COL_NORMAL) load_tw(s_twI, Gm::TWI, TwLayout<I>::size());
+    uint8_t mb[F::NB_out * F::R_out];
+#pragma unroll
+    for (int b = 0; b < F::NB_out; ++b) {
+      const int j = j0 + b * T;
+#pragma unroll
+      for (int r = 0; r < F::R_out; ++r) {
+        const int ky = j + r * F::B_out;
+        mb[b * F::R_out + r] =
+            lay_out_ok<F>(j) ? (MASK1D ? mask_s[ky] : mask_s[(size_t)ky * N + kx]) : (uint8_t)0;
+      }
+    }
+    twf.store(s_twF);
+    if constexpr (MODE == COL_NORMAL) twi.store(s_twI);
     __syncthreads();
     fft_run<F, -1, Gm::CPW>(v, bufc, j0, s_twF);
+#pragma unroll
+    for (int i = 0; i < F::NB_out * F::R_out; ++i)
+      if (mb[i] != 0) mbits |= 1u << i;
 #pragma unroll
     for (int b = 0; b < F::NB_out; ++b) {
       const int j = j0 + b * T;
@@ -368,6 +414,9 @@ __global__ __launch_bounds__(256, 2) void k_row_inv(const float2 *__restrict__ t
   float2 acc[Gm::P_IN];
 #pragma unroll
   for (int i = 0; i < Gm::P_IN; ++i) acc[i] = make_float2(0.f, 0.f);
+  // twiddles first: their LDS store then waits for them alone, not for the rows
+  TwRegs<TwLayout<I>::size(), Gm::THREADS> twi;
+  twi.fetch(Gm::TWI);
   const int iters = (Cs + cstep - 1) / cstep;
   for (int it = 0; it < iters; ++it) {
     const int c = cg + it * cstep;
@@ -391,7 +440,7 @@ __global__ __launch_bounds__(256, 2) void k_row_inv(const float2 *__restrict__ t
       for (int r = 0; r < I::R_out; ++r) sv[b * I::R_out + r] = ok ? sr[j + r * I::B_out] : make_float2(0.f, 0.f);
     }
     if (it == 0) {
-      load_tw(s_tw, Gm::TWI, TwLayout<I>::size());
+      twi.store(s_tw);
       __syncthreads();
     }
     fft_run<I, +1>(v, s_buf[opaque(g)], opaque(j0), s_tw);
@@ -453,6 +502,11 @@ __global__ __launch_bounds__(256, 2) void k_row_inv_fwd(float2 *__restrict__ t, 
   float2 acc[Gm::P_IN], sv[Gm::P_IN];
 #pragma unroll
   for (int i = 0; i < Gm::P_IN; ++i) acc[i] = make_float2(0.f, 0.f);
+  // twiddles first: their LDS store then waits for them alone, not for the rows
+  TwRegs<TwLayout<I>::size(), Gm::THREADS> twi;
+  TwRegs<TwLayout<F>::size(), Gm::THREADS> twf;
+  twi.fetch(Gm::TWI);
+  twf.fetch(Gm::TWF);
   const int iters = (Cs + cstep - 1) / cstep;
   for (int it = 0; it < iters; ++it) {
     const int c = cg + it * cstep;
@@ -476,8 +530,8 @@ __global__ __launch_bounds__(256, 2) void k_row_inv_fwd(float2 *__restrict__ t, 
       for (int r = 0; r < I::R_out; ++r) sv[b * I::R_out + r] = ok ? sr[j + r * I::B_out] : make_float2(0.f, 0.f);
     }
     if (it == 0) {
-      load_tw(s_twI, Gm::TWI, TwLayout<I>::size());
-      load_tw(s_twF, Gm::TWF, TwLayout<F>::size());
+      twi.store(s_twI);
+      twf.store(s_twF);
       __syncthreads();
     }
     fft_run<I, +1>(v, s_buf[opaque(g)], opaque(j0), s_twI);
@@ -854,9 +908,9 @@ __global__ __launch_bounds__(256) void k_nudft_adjoint(const float2 *__restrict_
 // texture address unit busy; the packed layout stores, per slice, the values in
 // the order the kernel's lanes consume them: [column block][coil][wave][pair p]
 // [lane][h], where lane l's element i = 2p + h is its natural value at row pos_i
-// (zero where the plan's layout has no row).  A wave then reads one coil's pair
-// p as 1 KB of contiguous bytes (64 lanes x 16 bytes).  Same size as the natural
-// layout.
+// (every slot holds a value: these plans have one input block of T rows).  A
+// wave then reads one coil's pair p as 1 KB of contiguous bytes (64 lanes x 16
+// bytes).  Same size as the natural layout.
 template <int N> struct Pack1D {
   using Gm = Geo1D<N>;
   using F = typename Gm::F;
@@ -901,9 +955,10 @@ __global__ __launch_bounds__(256) void k_pack_1d(const float2 *__restrict__ sens
 // One-pass normal operator for a phase-encode mask (sampled rows ky, all kx):
 // F^H M F = (F_y^H M_y F_y) (x) I, so each column only needs a y transform pair.
 // Block = COLS columns of one slice, wave-private transform groups; all coils
-// are accumulated in registers; the next coil map is loaded after the
-// current one has been transformed and combined.  PACKED: `sens` is in the
-// packed layout above (same arithmetic, so bitwise the same result).
+// are accumulated in registers; the next coil map is loaded while the current
+// one is transformed (packed) or after it has been combined (natural).  PACKED:
+// `sens` is in the packed layout above (same arithmetic, so bitwise the same
+// result).
 // The per-lane index math of the transforms stays in registers across the coil
 // loop (the compiler hoists it; recomputing it for every coil costs more).
 template <int N, bool PACKED>
