@@ -388,6 +388,16 @@ __global__ __launch_bounds__(256, 2) void k_col(float2 *__restrict__ t, const fl
 }
 
 // ---------------------------------------------------------------------------
+// The combine of a block of rpw rows gives thread e the outputs e, e + blockDim,
+// ...; its first w value is read together with the rows (at N = 256 with one row
+// per block it is the only one), so the combine does not wait for it.
+template <int N>
+__device__ __forceinline__ float2 first_w(const float2 *w, int rpw, int rows) {
+  if (!w || (int)threadIdx.x >= rpw * N) return make_float2(0.f, 0.f);
+  const int rr = blockIdx.x * rpw + (int)threadIdx.x / N;
+  return rr < rows ? w[(size_t)rr * N + threadIdx.x % N] : make_float2(0.f, 0.f);
+}
+
 // Pass 3: y[s, r, :] = alpha sum_c conj(S_c[s, r, :]) IDFT_x(t_c[s, r, :]) + beta w.
 // Block = rpw rows; transform group g handles row (g % rpw) and coils
 // g / rpw, g / rpw + G / rpw, ...; the groups are summed in a fixed order.
@@ -417,6 +427,7 @@ __global__ __launch_bounds__(256, 2) void k_row_inv(const float2 *__restrict__ t
   // twiddles first: their LDS store then waits for them alone, not for the rows
   TwRegs<TwLayout<I>::size(), Gm::THREADS> twi;
   twi.fetch(Gm::TWI);
+  float2 w0 = make_float2(0.f, 0.f);   // this thread's first w value of the combine
   const int iters = (Cs + cstep - 1) / cstep;
   for (int it = 0; it < iters; ++it) {
     const int c = cg + it * cstep;
@@ -440,6 +451,7 @@ __global__ __launch_bounds__(256, 2) void k_row_inv(const float2 *__restrict__ t
       for (int r = 0; r < I::R_out; ++r) sv[b * I::R_out + r] = ok ? sr[j + r * I::B_out] : make_float2(0.f, 0.f);
     }
     if (it == 0) {
+      w0 = first_w<N>(w, rpw, rows);
       twi.store(s_tw);
       __syncthreads();
     }
@@ -467,7 +479,7 @@ __global__ __launch_bounds__(256, 2) void k_row_inv(const float2 *__restrict__ t
     for (int q = 1; q < cstep; ++q) sum = cadd(sum, red[(q * rpw + r_o) * N + i]);
     float2 out = cscale(sum, alpha);
     const size_t o = (size_t)rr * N + i;
-    if (w) out = cadd(out, cscale(w[o], beta));
+    if (w) out = cadd(out, cscale(e == (int)threadIdx.x ? w0 : w[o], beta));
     y[o] = out;
   }
 }
@@ -507,6 +519,7 @@ __global__ __launch_bounds__(256, 2) void k_row_inv_fwd(float2 *__restrict__ t, 
   TwRegs<TwLayout<F>::size(), Gm::THREADS> twf;
   twi.fetch(Gm::TWI);
   twf.fetch(Gm::TWF);
+  float2 w0 = make_float2(0.f, 0.f);   // this thread's first w value of the combine
   const int iters = (Cs + cstep - 1) / cstep;
   for (int it = 0; it < iters; ++it) {
     const int c = cg + it * cstep;
@@ -530,6 +543,7 @@ __global__ __launch_bounds__(256, 2) void k_row_inv_fwd(float2 *__restrict__ t, 
       for (int r = 0; r < I::R_out; ++r) sv[b * I::R_out + r] = ok ? sr[j + r * I::B_out] : make_float2(0.f, 0.f);
     }
     if (it == 0) {
+      w0 = first_w<N>(w, rpw, rows);
       twi.store(s_twI);
       twf.store(s_twF);
       __syncthreads();
@@ -558,7 +572,7 @@ __global__ __launch_bounds__(256, 2) void k_row_inv_fwd(float2 *__restrict__ t, 
     float2 out = cscale(sum, alpha);
     if (rr < rows) {
       const size_t o = (size_t)rr * N + i;
-      if (w) out = cadd(out, cscale(w[o], beta));
+      if (w) out = cadd(out, cscale(e == (int)threadIdx.x ? w0 : w[o], beta));
       y[o] = out;
     }
     red[r_o * N + i] = out;
