@@ -643,6 +643,8 @@ __global__ __launch_bounds__(256) void k_trow_fwd(const float2 *__restrict__ x, 
   const int s = sy / N, yy = sy % N;
   const float2 *xr = x + (size_t)sy * N;
   const float2 *sr = sens + ((size_t)(s * C + c) * N + yy) * N;
+  TwRegs<TwLayout<F>::size(), Gm::THREADS> twf;   // twiddles first (see TwRegs)
+  twf.fetch(Gm::TWF);
   float2 v[Gm::P];
 #pragma unroll
   for (int b = 0; b < F::NB_in; ++b) {
@@ -654,7 +656,7 @@ __global__ __launch_bounds__(256) void k_trow_fwd(const float2 *__restrict__ x, 
       v[b * F::R_in + r] = (ok && i < N) ? cmul(sr[i], xr[i]) : make_float2(0.f, 0.f);
     }
   }
-  load_tw(s_tw, Gm::TWF, TwLayout<F>::size());
+  twf.store(s_tw);
   __syncthreads();
   fft_run<F, -1>(v, s_buf[g], j0, s_tw);
   float2 *tr = t + ((size_t)(s * C + c) * N + yy) * M;
@@ -697,6 +699,8 @@ __global__ __launch_bounds__(256, 2) void k_tcol(float2 *__restrict__ t, const f
       v[b * F::R_in + r] = (ok && yy < N) ? tc[(size_t)yy * M + kx] : make_float2(0.f, 0.f);
     }
   }
+  // (the kernel values are read after the forward transform: fetching them with
+  // the column measured slower, 15.3 against 14.1 us at M = 512)
   load_tw(s_twF, Gm::TWF, TwLayout<F>::size());
   load_tw(s_twI, Gm::TWI, TwLayout<I>::size());
   __syncthreads();
@@ -745,6 +749,8 @@ __global__ __launch_bounds__(256, 2) void k_trow_inv(const float2 *__restrict__ 
   float2 acc[Gm::P_IN];
 #pragma unroll
   for (int i = 0; i < Gm::P_IN; ++i) acc[i] = make_float2(0.f, 0.f);
+  TwRegs<TwLayout<I>::size(), Gm::THREADS> twi;   // twiddles first (see TwRegs)
+  twi.fetch(Gm::TWI);
   const int iters = (C + cstep - 1) / cstep;
   for (int it = 0; it < iters; ++it) {
     const int c = cg + it * cstep;
@@ -771,7 +777,7 @@ __global__ __launch_bounds__(256, 2) void k_trow_inv(const float2 *__restrict__ 
       }
     }
     if (it == 0) {
-      load_tw(s_tw, Gm::TWI, TwLayout<I>::size());
+      twi.store(s_tw);
       __syncthreads();
     }
     fft_run<I, +1>(v, s_buf[opaque(g)], opaque(j0), s_tw);
