@@ -1082,12 +1082,35 @@ __global__ __launch_bounds__(Geo1D<N>::THREADS, 2) void k_normal_1d(const float2
   }
   float2 *ys = y + (size_t)s * N * N;
   const float2 *ws = w ? w + (size_t)s * N * N : nullptr;
+  if constexpr (PACKED) {
+    // the block's outputs go through LDS so that y is written in whole row
+    // segments (a wave instruction covers four rows of the block's COLS
+    // columns) rather than 16 bytes of a row per wave, which let partly written
+    // lines leave the L2 early and be written twice
+    constexpr int TS = Gm::COLS + 1;   // padded tile row
+    static_assert(N * TS <= Gm::COLS * Gm::LDSN, "output tile fits the exchange buffer");
+    __syncthreads();
 #pragma unroll
-  for (int i = 0; i < PI; ++i) {
-    if (okp(i)) {
-      float2 out = cscale(acc[i], alpha);
-      if (ws) out = cadd(out, cscale(ws[pos(i)], beta));
-      ys[pos(i)] = out;
+    for (int i = 0; i < PI; ++i) {
+      if (okp(i)) {
+        float2 out = cscale(acc[i], alpha);
+        if (ws) out = cadd(out, cscale(ws[pos(i)], beta));
+        s_buf[(j0 + (i / F::R_in) * T + (i % F::R_in) * F::B_in) * TS + col] = out;
+      }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < N * Gm::COLS; e += Gm::THREADS) {
+      const int row = e / Gm::COLS, c = e % Gm::COLS;
+      ys[(size_t)row * N + blockIdx.x * Gm::COLS + c] = s_buf[row * TS + c];
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < PI; ++i) {
+      if (okp(i)) {
+        float2 out = cscale(acc[i], alpha);
+        if (ws) out = cadd(out, cscale(ws[pos(i)], beta));
+        ys[pos(i)] = out;
+      }
     }
   }
 }
