@@ -437,14 +437,14 @@ template <int N, int V = 0> struct Ops {
     col<pf::COL_RESID>(d, t, b, nullptr, mask, (float)(a / N), (float)b_scale, partials, st);
   }
 
-  // k_dev: a valid device int; use_k != 0 takes beta = k / (k + 3) from it;
-  // lam_s: per-slice thresholds (device) or nullptr for `lam`
   // natural -> packed coil maps of a phase-encode plan
   static void pack_1d(const Shape &d, const float2 *sens, float2 *out, hipStream_t st) {
     const dim3 grid(N / pf::Geo1D<N>::COLS, d.coils, d.slices);
     pf::k_pack_1d<N><<<grid, 256, 0, st>>>(sens, out, d.coils);
   }
 
+  // k_dev: a valid device int; use_k != 0 takes beta = k / (k + 3) from it;
+  // lam_s: per-slice thresholds (device) or nullptr for `lam`
   static void step(const Shape &d, const float2 *z, const float2 *pg, const float2 *xo, float2 *xn,
                    float2 *zn, float pg_scale, float lam, float beta, const int *k_dev, int use_k,
                    double *partials, hipStream_t st, const float *lam_s = nullptr) {
