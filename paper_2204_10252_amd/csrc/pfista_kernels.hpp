@@ -193,15 +193,25 @@ __global__ __launch_bounds__(256) void k_row_fwd(const float2 *__restrict__ x,
   const bool valid = task < tasks;
   int s, yy, cim;
   if (cb) {
+    // the per-slice image table goes to LDS in one round trip (for up to
+    // kRowCb - 1 slices), so the binary search below does not chain global loads
+    constexpr int kRowCb = 257;
+    __shared__ int s_cb[kRowCb];
+    const bool in_lds = slices < kRowCb;
+    if (in_lds) {
+      for (int i = threadIdx.x; i <= slices; i += Gm::THREADS) s_cb[i] = cb[i];
+      __syncthreads();
+    }
+    const int *tab = in_lds ? s_cb : cb;
     const int tk = valid ? task : 0;
     int lo = 0, hi = slices - 1;   // the slice whose task range holds tk
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (cb[mid] * N <= tk) lo = mid;
+      if (tab[mid] * N <= tk) lo = mid;
       else hi = mid - 1;
     }
     s = lo;
-    const int base = cb[s], cnum = cb[s + 1] - base;
+    const int base = tab[s], cnum = tab[s + 1] - base;
     const int local = tk - base * N;
     yy = local / cnum;
     cim = base + local % cnum;
