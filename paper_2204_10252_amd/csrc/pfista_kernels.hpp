@@ -573,7 +573,14 @@ __global__ __launch_bounds__(256, 2) void k_row_inv_fwd(float2 *__restrict__ t, 
     }
   }
   __syncthreads();
-  // combined rows: written out, and kept in the q = 0 slot of each row for the forward half
+  // combined rows: written out, and kept for the forward half in their own LDS
+  // rows when they fit (then the forward exchanges, which reuse the partial-sum
+  // area, need not wait for every group to have read them), else in the q = 0
+  // slot of each row
+  constexpr int KC = N <= 384 ? 2 * N : 1;
+  __shared__ float2 s_comb[KC];
+  const bool sep = rpw * N <= KC;
+  float2 *comb = sep ? s_comb : red;
   for (int e = threadIdx.x; e < rpw * N; e += blockDim.x) {
     const int r_o = e / N, i = e % N;
     const int rr = blockIdx.x * rpw + r_o;
@@ -585,7 +592,7 @@ __global__ __launch_bounds__(256, 2) void k_row_inv_fwd(float2 *__restrict__ t, 
       if (w) out = cadd(out, cscale(e == (int)threadIdx.x ? w0 : w[o], beta));
       y[o] = out;
     }
-    red[r_o * N + i] = out;
+    comb[r_o * N + i] = out;
   }
   __syncthreads();
   float2 yv[Gm::P_IN];
@@ -593,9 +600,9 @@ __global__ __launch_bounds__(256, 2) void k_row_inv_fwd(float2 *__restrict__ t, 
   for (int b = 0; b < F::NB_in; ++b) {
     const int j = j0 + b * T;
 #pragma unroll
-    for (int r = 0; r < F::R_in; ++r) yv[b * F::R_in + r] = lay_in_ok<F>(j) ? red[ro * N + j + r * F::B_in] : make_float2(0.f, 0.f);
+    for (int r = 0; r < F::R_in; ++r) yv[b * F::R_in + r] = lay_in_ok<F>(j) ? comb[ro * N + j + r * F::B_in] : make_float2(0.f, 0.f);
   }
-  __syncthreads();
+  if (!sep) __syncthreads();
   for (int it = 0; it < iters; ++it) {
     const int c = cg + it * cstep;
     const bool valid = rvalid && c < Cs;
