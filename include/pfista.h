@@ -151,8 +151,8 @@ int pfista_pack_coil_maps(const pfista_plan *p, const pfista_c32 *sens, pfista_c
  * the same order, so bitwise the same results.  UNSUPPORTED for other plans;
  * `packed` must be 16-byte aligned.  pfista_solve packs the maps into its
  * workspace by itself when it runs at least 12 normal applies
- * (max_iter * (degree + 1)); shorter solves read them in place, with the same
- * results. */
+ * (max_iter * (degree + 1), plus power_iters when inv_l = 0); shorter solves
+ * read them in place, with the same results. */
 int pfista_normal_apply_packed(const pfista_plan *p, const pfista_c32 *packed, const uint8_t *mask,
                                const pfista_c32 *x, pfista_c32 *y, float alpha, const pfista_c32 *w,
                                float beta, void *ws, hipStream_t stream);

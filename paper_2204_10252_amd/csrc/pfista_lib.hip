@@ -679,6 +679,44 @@ int check_packed_plan(const pfista_plan *p, const pfista_c32 *packed, const uint
   return PFISTA_OK;
 }
 
+// packed != 0: `sens` holds the packed coil maps of a phase-encode plan
+int power_iteration_impl(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *mask, pfista_c32 *v,
+                         int iters, double *lam_max, void *ws, hipStream_t stream, int packed) {
+  PF_TRY(check_ops(p, sens, mask, ws));
+  if (!lam_max) return fail(PFISTA_EINVAL, "lam_max is NULL");
+  if (p->d.slices == 0) {
+    *lam_max = 0.0;
+    return PFISTA_OK;
+  }
+  if (iters < 1) return fail(PFISTA_EINVAL, "iters must be >= 1");
+  const Layout L = layout(p->d);
+  if (L.n_img == 0) {
+    *lam_max = 0.0;
+    return PFISTA_OK;
+  }
+  if (v) PF_TRY(check_ptr(v, "v"));
+  float2 *cur = v ? F2(v) : at<float2>(ws, L.img[4]);
+  float2 *nxt = at<float2>(ws, L.img[3]);
+  double *partials = at<double>(ws, L.partials);
+  DevState *ds = at<DevState>(ws, L.state);
+  if (!v) pf::k_random<<<blocks_for(L.n_img), 256, 0, stream>>>(cur, L.n_img, 0ull);
+  norm2_dev(cur, L.n_img, partials, ds->misc, stream);
+  pf::k_normalise<<<blocks_for(L.n_img), 256, 0, stream>>>(cur, L.n_img, ds->misc);
+  for (int it = 0; it < iters; ++it) {
+    normal_op_t(p->d, sens, mask, cur, nxt, 1.f, nullptr, 0.f, at<float2>(ws, L.t), stream, nullptr, packed);
+    norm2_dev(nxt, L.n_img, partials, ds->misc, stream);
+    pf::k_normalise<<<blocks_for(L.n_img), 256, 0, stream>>>(nxt, L.n_img, ds->misc);
+    std::swap(cur, nxt);
+  }
+  PF_TRY(launch_status("pfista_power_iteration"));
+  if (v && cur != F2(v)) PF_HIP(hipMemcpyAsync(v, cur, L.n_img * sizeof(float2), hipMemcpyDeviceToDevice, stream));
+  double h = 0.0;
+  PF_HIP(hipMemcpyAsync(&h, ds->misc, sizeof(double), hipMemcpyDeviceToHost, stream));
+  PF_HIP(hipStreamSynchronize(stream));
+  *lam_max = std::sqrt(h);
+  return PFISTA_OK;
+}
+
 }  // namespace
 
 // ============================================================================ C-ABI
@@ -944,40 +982,9 @@ int pfista_data_term(const pfista_plan *p, const pfista_c32 *sens, const uint8_t
 
 int pfista_power_iteration(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *mask, pfista_c32 *v,
                            int iters, double *lam_max, void *ws, hipStream_t stream) {
-  PF_TRY(check_ops(p, sens, mask, ws));
-  if (!lam_max) return fail(PFISTA_EINVAL, "lam_max is NULL");
-  if (p->d.slices == 0) {
-    *lam_max = 0.0;
-    return PFISTA_OK;
-  }
-  if (iters < 1) return fail(PFISTA_EINVAL, "iters must be >= 1");
-  const Layout L = layout(p->d);
-  if (L.n_img == 0) {
-    *lam_max = 0.0;
-    return PFISTA_OK;
-  }
-  if (v) PF_TRY(check_ptr(v, "v"));
-  float2 *cur = v ? F2(v) : at<float2>(ws, L.img[4]);
-  float2 *nxt = at<float2>(ws, L.img[3]);
-  double *partials = at<double>(ws, L.partials);
-  DevState *ds = at<DevState>(ws, L.state);
-  if (!v) pf::k_random<<<blocks_for(L.n_img), 256, 0, stream>>>(cur, L.n_img, 0ull);
-  norm2_dev(cur, L.n_img, partials, ds->misc, stream);
-  pf::k_normalise<<<blocks_for(L.n_img), 256, 0, stream>>>(cur, L.n_img, ds->misc);
-  for (int it = 0; it < iters; ++it) {
-    normal_op(p->d, sens, mask, cur, nxt, 1.f, nullptr, 0.f, ws, stream);
-    norm2_dev(nxt, L.n_img, partials, ds->misc, stream);
-    pf::k_normalise<<<blocks_for(L.n_img), 256, 0, stream>>>(nxt, L.n_img, ds->misc);
-    std::swap(cur, nxt);
-  }
-  PF_TRY(launch_status("pfista_power_iteration"));
-  if (v && cur != F2(v)) PF_HIP(hipMemcpyAsync(v, cur, L.n_img * sizeof(float2), hipMemcpyDeviceToDevice, stream));
-  double h = 0.0;
-  PF_HIP(hipMemcpyAsync(&h, ds->misc, sizeof(double), hipMemcpyDeviceToHost, stream));
-  PF_HIP(hipStreamSynchronize(stream));
-  *lam_max = std::sqrt(h);
-  return PFISTA_OK;
+  return power_iteration_impl(p, sens, mask, v, iters, lam_max, ws, stream, 0);
 }
+
 
 int pfista_profile_normal(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *mask,
                           const pfista_c32 *x, pfista_c32 *y, int reps, float *pass_ms, int *npasses, void *ws,
@@ -1092,10 +1099,24 @@ int pfista_solve(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *ma
     bnorm = std::sqrt(h[0]);
   }
   r.bnorm = bnorm;
+  // phase-encode plans: the loop (and the power iteration) read the coil maps in
+  // the packed layout when the solve runs enough applies to repay the packing
+  // (one read and one write of the maps, about what 11 applies save); the
+  // results are the same bit for bit
+  const long long solve_applies =
+      (long long)prm->max_iter * (long long)c.size() + (prm->inv_l == 0.0 ? prm->power_iters : 0);
+  const int packed = d.mask_kind == PFISTA_MASK_1D && solve_applies >= kPackMinApplies ? 1 : 0;
+  const pfista_c32 *loop_sens = sens;
+  if (packed) {
+    pfista_c32 *spk = at<pfista_c32>(ws, solve_packed_off(d));
+    PF_DISPATCH(d.n, Ops<NN>::pack_1d(shape_of(d), F2(sens), F2(spk), stream));
+    PF_TRY(launch_status("pfista_solve(pack)"));
+    loop_sens = spk;
+  }
   double inv_l = prm->inv_l;
   if (inv_l == 0.0) {
     double lam = 0.0;
-    PF_TRY(pfista_power_iteration(p, sens, mask, nullptr, prm->power_iters, &lam, ws, stream));
+    PF_TRY(power_iteration_impl(p, loop_sens, mask, nullptr, prm->power_iters, &lam, ws, stream, packed));
     if (!(lam > 0.0)) return fail(PFISTA_EINVAL, "power iteration gave %g", lam);
     inv_l = 1.0 / (1.01 * lam);
   }
@@ -1120,18 +1141,6 @@ int pfista_solve(const pfista_plan *p, const pfista_c32 *sens, const uint8_t *ma
   set_counter(ds, k0 - 1, stream);   // the first gradient apply advances it to k0
   PF_TRY(launch_status("pfista_solve(setup)"));
 
-  // phase-encode plans: the loop reads the coil maps in the packed layout when
-  // the solve is long enough to repay the packing (one read and one write of the
-  // maps, about what 11 applies save); the results are the same bit for bit
-  const long long solve_applies = (long long)prm->max_iter * (long long)c.size();
-  const int packed = d.mask_kind == PFISTA_MASK_1D && solve_applies >= kPackMinApplies ? 1 : 0;
-  const pfista_c32 *loop_sens = sens;
-  if (packed) {
-    pfista_c32 *spk = at<pfista_c32>(ws, solve_packed_off(d));
-    PF_DISPATCH(d.n, Ops<NN>::pack_1d(shape_of(d), F2(sens), F2(spk), stream));
-    PF_TRY(launch_status("pfista_solve(pack)"));
-    loop_sens = spk;
-  }
   const int deg = (int)c.size() - 1;
   const float lam = (float)prm->lambda;
   const int nstep = (d.n / 16) * (d.n / 16) * d.slices;

@@ -149,3 +149,21 @@ def test_packed_solve_equals_resumed_solves_on_natural_maps():
         pf.solve(plan, ts, tm, b, x2, lam=1e-3, degree=2, max_iter=1, inv_l=0.9, z=z2, k0=k, check_every=1)
     assert _same_bits(x1, x2) and _same_bits(z1, z2)
     assert torch.isfinite(torch.view_as_real(x1)).all()
+
+
+def test_solver_power_iteration_on_packed_maps_matches_the_public_one():
+    """A phase-encode solve that estimates L (inv_l = 0) packs first and runs its
+    power iteration on the packed maps: the estimate equals the public power
+    iteration's (natural maps, same start vector) bit for bit."""
+    import torch
+    import paper_2204_10252_amd as pf
+    n, coils = 160, 5
+    sens, mask, x, _ = random_case(n, coils, 2, "1d", seed=21)
+    plan = pf.Plan(n, coils, 2, haar_levels=3, mask_kind=pf.MASK_1D)
+    ts, tm = to_dev(sens), to_dev(mask)
+    b = torch.empty((2, coils, n, n), dtype=torch.complex64, device=ts.device)
+    pf.forward(plan, ts, tm, to_dev(x), b)
+    lam = pf.power_iteration(plan, ts, tm, 20)
+    xo = torch.empty((2, n, n), dtype=torch.complex64, device=ts.device)
+    rep = pf.solve(plan, ts, tm, b, xo, lam=1e-3, degree=1, max_iter=1, inv_l=0.0, power_iters=20)
+    assert rep["inv_l"] == 1.0 / (1.01 * lam)
