@@ -122,6 +122,20 @@ __device__ __forceinline__ void load_tw(float2 *dst, int off, int count) {
   for (int i = threadIdx.x; i < count; i += blockDim.x) dst[i] = g_tw[off + i];
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin (block b to XCD b % 8), so
+// consecutive blocks land on different L2s.  The row passes and the step number
+// their blocks through xcd_block: block b takes work item (b % 8) * (nb / 8) +
+// b / 8, which gives each XCD one contiguous eighth of the rows (of the step's
+// tiles), the same eighth in every row pass and in the step; the rows a pass
+// reads (coil maps, the step's output) are then the ones its XCD's L2 saw in the
+// previous row-mapped kernel.  Any numbering is correct; this one is only faster.
+// The inverse row passes of a batch group (the CB kernels) keep the plain numbering:
+// there a row costs in proportion to its slice's coil count, and contiguous
+// eighths would leave the XCD holding the many-coil slices running alone, while
+// round-robin blocks spread every slice over all eight.  Passing nb = 1 selects
+// the plain numbering.
+__device__ __forceinline__ int xcd_block(int b, int nb) { return (nb % 8) ? b : (b % 8) * (nb / 8) + b / 8; }
+
 // A twiddle table fetched into registers first and stored to LDS later: global
 // loads issued in between stay in flight across the store (a load_tw right after
 // them would wait for all of them).
@@ -175,7 +189,10 @@ template <class PL> __device__ __forceinline__ bool lay_out_ok(int j) {
 // fastest, so the transform groups of a block share rows of x.  With per-slice
 // coil counts slice s owns tasks cb[s]*N .. cb[s+1]*N - 1.
 // A transform group is T consecutive lanes of one wave (wave-level hand-over).
-template <int N, int V = 0>
+// CB: the launch carries the per-slice image table cb (a batch group); the row
+// kernels are also compiled without it, for launches whose slices share one
+// coil count (cb = nullptr), so that those carry no table code.
+template <int N, int V = 0, bool CB = false>
 __global__ __launch_bounds__(256) void k_row_fwd(const float2 *__restrict__ x,
                                                  const float2 *__restrict__ sens,
                                                  float2 *__restrict__ t, int C, int tasks,
@@ -185,11 +202,12 @@ __global__ __launch_bounds__(256) void k_row_fwd(const float2 *__restrict__ x,
   // the solver's iteration counter: advanced here, read by the step kernel of
   // the same iteration (stream order separates the two)
   if (k_inc && blockIdx.x == 0 && threadIdx.x == 0) *k_inc += 1;
+  if constexpr (!CB) cb = nullptr;
   constexpr int T = Gm::T;
   __shared__ float2 s_tw[TwLayout<F>::size()];
   __shared__ float2 s_buf[Gm::G][Gm::LDSN];
   const int g = threadIdx.x / T, j0 = threadIdx.x % T;
-  const int task = blockIdx.x * Gm::G + g;
+  const int task = xcd_block(blockIdx.x, gridDim.x) * Gm::G + g;
   const bool valid = task < tasks;
   int s, yy, cim;
   if (cb) {
@@ -402,16 +420,16 @@ __global__ __launch_bounds__(256, 2) void k_col(float2 *__restrict__ t, const fl
 // ...; its first w value is read together with the rows (at N = 256 with one row
 // per block it is the only one), so the combine does not wait for it.
 template <int N>
-__device__ __forceinline__ float2 first_w(const float2 *w, int rpw, int rows) {
+__device__ __forceinline__ float2 first_w(const float2 *w, int rpw, int rows, int nb) {
   if (!w || (int)threadIdx.x >= rpw * N) return make_float2(0.f, 0.f);
-  const int rr = blockIdx.x * rpw + (int)threadIdx.x / N;
+  const int rr = xcd_block(blockIdx.x, nb) * rpw + (int)threadIdx.x / N;
   return rr < rows ? w[(size_t)rr * N + threadIdx.x % N] : make_float2(0.f, 0.f);
 }
 
 // Pass 3: y[s, r, :] = alpha sum_c conj(S_c[s, r, :]) IDFT_x(t_c[s, r, :]) + beta w.
 // Block = rpw rows; transform group g handles row (g % rpw) and coils
 // g / rpw, g / rpw + G / rpw, ...; the groups are summed in a fixed order.
-template <int N, int V = 0>
+template <int N, int V = 0, bool CB = false>
 __global__ __launch_bounds__(256, 2) void k_row_inv(const float2 *__restrict__ t,
                                                  const float2 *__restrict__ sens,
                                                  float2 *__restrict__ y, const float2 *w, float alpha,
@@ -425,7 +443,9 @@ __global__ __launch_bounds__(256, 2) void k_row_inv(const float2 *__restrict__ t
   __shared__ float2 s_buf[G][Gm::LDSN];
   const int g = threadIdx.x / T, j0 = threadIdx.x % T;
   const int ro = g % rpw, cg = g / rpw, cstep = G / rpw;
-  const int row = blockIdx.x * rpw + ro;
+  if constexpr (!CB) cb = nullptr;
+  const int nb = CB ? 1 : (int)gridDim.x;
+  const int row = xcd_block(blockIdx.x, nb) * rpw + ro;
   const bool rvalid = row < rows;
   const int s = rvalid ? row / N : 0, yy = rvalid ? row % N : 0;
   // this slice's coil images (every row of a block lies in one slice: rpw divides N)
@@ -461,7 +481,7 @@ __global__ __launch_bounds__(256, 2) void k_row_inv(const float2 *__restrict__ t
       for (int r = 0; r < I::R_out; ++r) sv[b * I::R_out + r] = ok ? sr[j + r * I::B_out] : make_float2(0.f, 0.f);
     }
     if (it == 0) {
-      w0 = first_w<N>(w, rpw, rows);
+      w0 = first_w<N>(w, rpw, rows, nb);
       twi.store(s_tw);
       __syncthreads();
     }
@@ -483,7 +503,7 @@ __global__ __launch_bounds__(256, 2) void k_row_inv(const float2 *__restrict__ t
   __syncthreads();
   for (int e = threadIdx.x; e < rpw * N; e += blockDim.x) {
     const int r_o = e / N, i = e % N;
-    const int rr = blockIdx.x * rpw + r_o;
+    const int rr = xcd_block(blockIdx.x, nb) * rpw + r_o;
     if (rr >= rows) continue;
     float2 sum = red[r_o * N + i];
     for (int q = 1; q < cstep; ++q) sum = cadd(sum, red[(q * rpw + r_o) * N + i]);
@@ -500,7 +520,7 @@ __global__ __launch_bounds__(256, 2) void k_row_inv(const float2 *__restrict__ t
 //   y[s, r, :] = alpha sum_c conj(S_c) IDFT_x(t_c[s, r, :]) + beta w[s, r, :]
 //   t_c[s, r, :] = DFT_x(S_c[s, r, :] y[s, r, :])            (in place)
 // The row's coil maps are read once for both halves.
-template <int N, int V = 0>
+template <int N, int V = 0, bool CB = false>
 __global__ __launch_bounds__(256, 2) void k_row_inv_fwd(float2 *__restrict__ t, const float2 *__restrict__ sens,
                                                         float2 *__restrict__ y, const float2 *w, float alpha,
                                                         float beta, int C, int rows, int rpw,
@@ -516,7 +536,9 @@ __global__ __launch_bounds__(256, 2) void k_row_inv_fwd(float2 *__restrict__ t, 
   __shared__ float2 s_buf[G][Gm::LDSN];
   const int g = threadIdx.x / T, j0 = threadIdx.x % T;
   const int ro = g % rpw, cg = g / rpw, cstep = G / rpw;
-  const int row = blockIdx.x * rpw + ro;
+  if constexpr (!CB) cb = nullptr;
+  const int nb = CB ? 1 : (int)gridDim.x;
+  const int row = xcd_block(blockIdx.x, nb) * rpw + ro;
   const bool rvalid = row < rows;
   const int s = rvalid ? row / N : 0, yy = rvalid ? row % N : 0;
   const int cbase = cb ? cb[s] : s * C;
@@ -553,7 +575,7 @@ __global__ __launch_bounds__(256, 2) void k_row_inv_fwd(float2 *__restrict__ t, 
       for (int r = 0; r < I::R_out; ++r) sv[b * I::R_out + r] = ok ? sr[j + r * I::B_out] : make_float2(0.f, 0.f);
     }
     if (it == 0) {
-      w0 = first_w<N>(w, rpw, rows);
+      w0 = first_w<N>(w, rpw, rows, nb);
       twi.store(s_twI);
       twf.store(s_twF);
       __syncthreads();
@@ -583,7 +605,7 @@ __global__ __launch_bounds__(256, 2) void k_row_inv_fwd(float2 *__restrict__ t, 
   float2 *comb = sep ? s_comb : red;
   for (int e = threadIdx.x; e < rpw * N; e += blockDim.x) {
     const int r_o = e / N, i = e % N;
-    const int rr = blockIdx.x * rpw + r_o;
+    const int rr = xcd_block(blockIdx.x, nb) * rpw + r_o;
     float2 sum = red[r_o * N + i];
     for (int q = 1; q < cstep; ++q) sum = cadd(sum, red[(q * rpw + r_o) * N + i]);
     float2 out = cscale(sum, alpha);
@@ -1226,10 +1248,13 @@ __global__ __launch_bounds__(64) void k_step(const float2 *__restrict__ z, const
                                              double *__restrict__ partials,
                                              const float *__restrict__ lam_s) {
   const int lane = threadIdx.x, tx = lane & 7, ty = lane >> 3;
-  const int s = blockIdx.z;
+  // tiles numbered over all slices like the row passes' blocks (xcd_block)
+  const int ntile = gridDim.x * gridDim.y;
+  const int tg = xcd_block((blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x, ntile * gridDim.z);
+  const int s = tg / ntile, tl = tg % ntile;
   // per-slice threshold when a table is given
   const float lam = lam_s ? lam_s[s] : lam_arg;
-  const int px = blockIdx.x * 16 + 2 * tx, py = blockIdx.y * 16 + 2 * ty;
+  const int px = (tl % gridDim.x) * 16 + 2 * tx, py = (tl / gridDim.x) * 16 + 2 * ty;
   const size_t o0 = (size_t)s * N * N + (size_t)py * N + px, o1 = o0 + N;
   // unconditional scalar load: its latency overlaps the vector loads below
   const int kk = *k_dev;
@@ -1270,7 +1295,7 @@ __global__ __launch_bounds__(64) void k_step(const float2 *__restrict__ z, const
   // per-lane sums (a few FP32 terms each) widen to FP64 for the wave and grid sums
   const double l1d = wave_sum((double)l1), dx2d = wave_sum((double)dx2), xn2d = wave_sum((double)xn2);
   if (lane == 0) {
-    const size_t blk = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    const size_t blk = (size_t)tg;   // partial sums in tile order, whatever the block order
     partials[3 * blk + 0] = l1d;
     partials[3 * blk + 1] = dx2d;
     partials[3 * blk + 2] = xn2d;

@@ -298,7 +298,8 @@ template <int N, int V = 0> struct Ops {
                       int *k_inc = nullptr) {
     const int tasks = d.images * N;
     const int grid = (tasks + Gm::G - 1) / Gm::G;
-    pf::k_row_fwd<N, V><<<grid, Gm::THREADS, 0, st>>>(x, sens, t, d.coils, tasks, k_inc, d.cb, d.slices);
+    if (d.cb) pf::k_row_fwd<N, V, true><<<grid, Gm::THREADS, 0, st>>>(x, sens, t, d.coils, tasks, k_inc, d.cb, d.slices);
+    else pf::k_row_fwd<N, V, false><<<grid, Gm::THREADS, 0, st>>>(x, sens, t, d.coils, tasks, k_inc, nullptr, d.slices);
   }
 
   template <int MODE>
@@ -329,7 +330,8 @@ template <int N, int V = 0> struct Ops {
     const int rpw = rows_per_block(d);
     const int rows = d.slices * N;
     const int grid = (rows + rpw - 1) / rpw;
-    pf::k_row_inv<N, V><<<grid, Gm::THREADS, 0, st>>>(t, sens, y, w, alpha, beta, d.coils, rows, rpw, d.cb);
+    if (d.cb) pf::k_row_inv<N, V, true><<<grid, Gm::THREADS, 0, st>>>(t, sens, y, w, alpha, beta, d.coils, rows, rpw, d.cb);
+    else pf::k_row_inv<N, V, false><<<grid, Gm::THREADS, 0, st>>>(t, sens, y, w, alpha, beta, d.coils, rows, rpw, nullptr);
   }
 
   static void row_inv_fwd(const Shape &d, float2 *t, const float2 *sens, float2 *y, const float2 *w,
@@ -337,7 +339,8 @@ template <int N, int V = 0> struct Ops {
     const int rpw = rows_per_block(d);
     const int rows = d.slices * N;
     const int grid = (rows + rpw - 1) / rpw;
-    pf::k_row_inv_fwd<N, V><<<grid, Gm::THREADS, 0, st>>>(t, sens, y, w, alpha, beta, d.coils, rows, rpw, d.cb);
+    if (d.cb) pf::k_row_inv_fwd<N, V, true><<<grid, Gm::THREADS, 0, st>>>(t, sens, y, w, alpha, beta, d.coils, rows, rpw, d.cb);
+    else pf::k_row_inv_fwd<N, V, false><<<grid, Gm::THREADS, 0, st>>>(t, sens, y, w, alpha, beta, d.coils, rows, rpw, nullptr);
   }
 
   // A chain of m normal applies in which apply k+1's input is apply k's output:
