@@ -1308,9 +1308,13 @@ struct pfista_batch {
 
 namespace {
 
-// the launch shape of tuning candidate `cand` for a group
+// the launch shape of tuning candidate `cand` for a group; a group whose slices
+// share one coil count is laid out like a plan's slices and launches without
+// the coil tables (the kernels built for that case carry no table code)
 Shape group_shape(const BGroup &G, void *ws, int cand) {
-  return Shape{G.slices(), G.cmax, G.images, G.levels, PFISTA_MASK_2D, at<int>(ws, G.o_cb), at<int>(ws, G.o_cs),
+  const bool uniform = G.cmin == G.cmax;
+  return Shape{G.slices(), G.cmax, G.images, G.levels, PFISTA_MASK_2D,
+               uniform ? nullptr : at<int>(ws, G.o_cb), uniform ? nullptr : at<int>(ws, G.o_cs),
                G.cmin, 1 << (cand / 4), (cand / 2) % 2 ? 0 : 1};
 }
 
