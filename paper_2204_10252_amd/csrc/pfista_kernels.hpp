@@ -389,7 +389,33 @@ __global__ __launch_bounds__(256, 2) void k_col(float2 *__restrict__ t, const fl
     }
   }
 
-  if constexpr (MODE == COL_NORMAL || MODE == COL_ADJ_IN) {
+  if constexpr (MODE == COL_NORMAL) {
+    fft_run<I, +1, Gm::CPW>(v, bufc, j0, s_twI);
+    // Output through the waves' exchange regions (column c of the block at
+    // region c / CPW, element y at offset y * CPW + c % CPW), then written as
+    // whole row segments, two adjacent columns per thread: a wave's direct store
+    // would cover 32 bytes of each of 16 lines, and the block's four waves would
+    // fill every line in four partial writes.
+    constexpr int TPR = Gm::COLS / 2, RPI = Gm::THREADS / TPR, NL = (N + RPI - 1) / RPI;
+    const int sq = threadIdx.x % TPR, sr0 = threadIdx.x / TPR;
+    const float2 *ssrc = s_buf + (2 * sq / Gm::CPW) * Gm::CPW * Gm::LDSN + (2 * sq) % Gm::CPW;
+#pragma unroll
+    for (int b = 0; b < I::NB_out; ++b) {
+      const int j = j0 + b * T;
+      if (lay_out_ok<I>(j)) {
+#pragma unroll
+        for (int r = 0; r < I::R_out; ++r) bufc[(j + r * I::B_out) * Gm::CPW] = v[b * I::R_out + r];
+      }
+    }
+    __syncthreads();
+    float4 *dst = reinterpret_cast<float4 *>(tc + blockIdx.x * Gm::COLS) + sq;
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      const int yy = sr0 + k * RPI;
+      if (yy < N) dst[(size_t)yy * (N / 2)] = *reinterpret_cast<const float4 *>(ssrc + yy * Gm::CPW);
+    }
+  }
+  if constexpr (MODE == COL_ADJ_IN) {
     fft_run<I, +1, Gm::CPW>(v, bufc, j0, s_twI);
 #pragma unroll
     for (int b = 0; b < I::NB_out; ++b) {
