@@ -180,6 +180,32 @@ def test_every_forced_launch_shape_matches_oracle(c1, tune):
     assert rel(x.cpu().numpy(), xo) <= 1e-4
 
 
+@pytest.mark.parametrize("n", [160, 192, 256, 320, 384, 512])
+@pytest.mark.parametrize("tune", [2, 4])
+def test_second_radix_schedule_at_every_image_side_matches_oracle(n, tune):
+    # candidates 1 and 3 (fused and separate row passes) run the radix schedules
+    # with twice the lanes per transform, whose column pass has half as many
+    # columns per workgroup; every image side of the library, 2-D masks
+    import torch
+    import paper_2204_10252_amd as pf
+    from tests.gpu_util import random_case
+    sens, mask, img, _ = random_case(n, 3, 1, "2d", seed=900 + n + tune)
+    s128 = sens.astype(np.complex128)
+    noise = 1e-3 * np.random.default_rng(n).standard_normal(s128.shape)
+    b = c64(orc.kspace_data(s128, mask, img.astype(np.complex128), noise))
+    bn = b.astype(np.complex128) / np.linalg.norm(b.astype(np.complex128))
+    inv_l = 1.0 / 1.01   # coil maps with sum |S|^2 = 1 and a 0/1 mask: ||A^H A|| <= 1
+    lam, levels, iters = 1e-3, 4, 6
+    coef = [float(c) for c in orc.l2_poly_coefficients(2)]
+    plan = pf.Plan(n, 3, 1, haar_levels=levels)
+    x = torch.empty((1, n, n), dtype=torch.complex64, device="cuda")
+    rep = pf.solve(plan, to_dev(sens), to_dev(mask), to_dev(b), x, lam, coef=coef,
+                   max_iter=iters, inv_l=inv_l, tune=tune)
+    assert rep["candidate"] == tune - 1
+    xo, _, _ = orc.pfista(s128, mask, bn, inv_l, lam, coef, levels, iters)
+    assert rel(x.cpu().numpy(), xo) <= 1e-4
+
+
 def test_tuned_solve_workload2_is_cached_and_matches_oracle():
     import torch
     import paper_2204_10252_amd as pf
